@@ -1,0 +1,266 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes wrapper of the plain FP64 CPU oracle.
+
+The oracle (``lbm_oracle.c``) is a slow, dense-matrix reference of the coupled
+density / total-energy D2Q9 MRT scheme of Huang, Wu & Adams (arXiv:1809.08683,
+Secs. 2-3).  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may use it; the HIP library never does.
+
+Cases are plain dicts (see ``paper_1809_08683_amd.inputs``) so that the oracle
+and the library are driven by the same seeded inputs without sharing code.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.c")
+_LIB = os.path.join(_HERE, "liblbm_oracle.so")
+
+EOS = {"decoupled": 0, "ideal": 1, "vdw": 2, "cs": 3}
+VISC = {"const": 0, "linear": 1, "sutherland": 2}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (gcc, FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int),
+        ("eos", C.c_int), ("R", C.c_double), ("rho0", C.c_double), ("T0", C.c_double),
+        ("a", C.c_double), ("b", C.c_double),
+        ("Pr", C.c_double), ("gamma", C.c_double),
+        ("nu0", C.c_double), ("bulk_ratio", C.c_double),
+        ("visc_law", C.c_int), ("suth_S", C.c_double),
+        ("fx", C.c_double), ("fy", C.c_double), ("per_mass", C.c_int),
+        ("cubic", C.c_int), ("cp", C.c_double), ("cv_rule", C.c_int),
+        ("side_wall", C.c_int * 4), ("side_ux", C.c_double * 4), ("side_uy", C.c_double * 4),
+        ("side_adiabatic", C.c_int * 4), ("side_T", C.c_double * 4),
+        ("extrap_order", C.c_int),
+    ]
+
+
+class Derived(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "cs2", "R", "cp", "cv", "kappa", "mu0",
+        "alpha1", "beta1", "alpha2", "beta2", "varpi", "k", "h", "b", "gamma1", "gamma2")]
+
+
+_lib = None
+_D = C.POINTER(C.c_double)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=False)
+        lib = C.CDLL(_LIB)
+        vp = C.c_void_p
+        lib.orc_create.argtypes = [C.POINTER(_Params), C.POINTER(vp)]
+        lib.orc_destroy.argtypes = [vp]
+        lib.orc_error.argtypes = [vp]
+        lib.orc_error.restype = C.c_char_p
+        lib.orc_get_derived.argtypes = [vp, C.POINTER(Derived)]
+        lib.orc_init.argtypes = [vp, _D, _D, _D, _D]
+        lib.orc_step.argtypes = [vp, C.c_longlong]
+        lib.orc_time.argtypes = [vp]
+        lib.orc_time.restype = C.c_longlong
+        lib.orc_macros.argtypes = [vp, _D, _D, _D, _D, _D]
+        lib.orc_get_df.argtypes = [vp, _D, _D]
+        lib.orc_nusselt.argtypes = [vp, C.c_int, _D]
+        lib.orc_totals.argtypes = [vp, _D, _D, _D, _D]
+        lib.orc_lattice.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int), _D]
+        lib.orc_moment_matrix.argtypes = [_D, _D]
+        lib.orc_pressure.argtypes = [vp, C.c_double, C.c_double]
+        lib.orc_pressure.restype = C.c_double
+        lib.orc_meq.argtypes = [vp] + [C.c_double] * 4 + [_D]
+        lib.orc_fm.argtypes = [vp] + [C.c_double] * 4 + [_D]
+        lib.orc_neq.argtypes = [vp] + [C.c_double] * 6 + [_D]
+        lib.orc_qm.argtypes = [vp] + [C.c_double] * 3 + [_D]
+        lib.orc_rates.argtypes = [vp, C.c_double, C.c_double, _D]
+        lib.orc_matrices.argtypes = [vp] + [C.c_double] * 4 + [_D] * 6
+        lib.orc_collide_node.argtypes = [vp] + [_D] * 9
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _vec(n):
+    return np.zeros(n, dtype=np.float64)
+
+
+def params_from_case(case: dict) -> _Params:
+    p = _Params()
+    p.nx, p.ny = int(case["nx"]), int(case["ny"])
+    p.eos = EOS[case.get("eos", "ideal")]
+    p.R = float(case.get("R", 0.0))
+    p.rho0 = float(case.get("rho0", 1.0))
+    p.T0 = float(case.get("T0", 1.0))
+    p.a = float(case.get("a", 0.0))
+    p.b = float(case.get("b", 0.0))
+    p.Pr = float(case["Pr"])
+    p.gamma = float(case["gamma"])
+    p.nu0 = float(case["nu0"])
+    p.bulk_ratio = float(case.get("bulk_ratio", 1.0))
+    p.visc_law = VISC[case.get("visc_law", "const")]
+    p.suth_S = float(case.get("suth_S", 0.0))
+    fx, fy = case.get("force", (0.0, 0.0))
+    p.fx, p.fy = float(fx), float(fy)
+    p.per_mass = int(bool(case.get("per_mass", False)))
+    p.cubic = int(case.get("cubic", 2))
+    p.cp = float(case.get("cp", 0.0))
+    p.cv_rule = int(case.get("cv_rule", 0))
+    sides = case["sides"]
+    for s in range(4):
+        sd = sides[s]
+        p.side_wall[s] = 1 if sd["kind"] == "wall" else 0
+        u = sd.get("u", (0.0, 0.0))
+        p.side_ux[s], p.side_uy[s] = float(u[0]), float(u[1])
+        p.side_adiabatic[s] = 1 if sd.get("thermal", "dirichlet") == "adiabatic" else 0
+        p.side_T[s] = float(sd.get("T", case.get("T0", 1.0)))
+    p.extrap_order = int(case.get("extrap_order", 2))
+    return p
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Oracle:
+    """One oracle context.  Fields are returned as [ny, nx] float64 arrays."""
+
+    def __init__(self, case: dict):
+        self.lib = _load()
+        self.case = dict(case)
+        self.nx, self.ny = int(case["nx"]), int(case["ny"])
+        self._p = params_from_case(case)
+        h = C.c_void_p()
+        rc = self.lib.orc_create(C.byref(self._p), C.byref(h))
+        self.h = h
+        if rc != 0:
+            msg = self.lib.orc_error(h).decode() if h.value else "create failed"
+            self.lib.orc_destroy(h)
+            self.h = None
+            raise OracleError(f"orc_create: {rc}: {msg}")
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and getattr(self, "lib", None) is not None:
+            self.lib.orc_destroy(self.h)
+            self.h = None
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise OracleError(f"{what}: {rc}: {self.lib.orc_error(self.h).decode()}")
+
+    # ---- state ----
+    def init(self, rho=None, ux=None, uy=None, T=None):
+        conv = [None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+                for a in (rho, ux, uy, T)]
+        self._check(self.lib.orc_init(self.h, *[_ptr(a) for a in conv]), "orc_init")
+        return self
+
+    def step(self, n: int = 1):
+        rc = self.lib.orc_step(self.h, int(n))
+        if rc == -4:
+            raise OracleError(f"diverged at t={self.time}")
+        self._check(rc, "orc_step")
+        return self
+
+    @property
+    def time(self) -> int:
+        return int(self.lib.orc_time(self.h))
+
+    def macros(self) -> dict:
+        nn = self.nx * self.ny
+        out = {k: _vec(nn) for k in ("rho", "ux", "uy", "T", "p")}
+        self._check(self.lib.orc_macros(self.h, *[_ptr(out[k]) for k in ("rho", "ux", "uy", "T", "p")]),
+                    "orc_macros")
+        return {k: v.reshape(self.ny, self.nx) for k, v in out.items()}
+
+    def df(self):
+        nn = self.nx * self.ny
+        f, g = _vec(nn * 9), _vec(nn * 9)
+        self._check(self.lib.orc_get_df(self.h, _ptr(f), _ptr(g)), "orc_get_df")
+        return f.reshape(self.ny, self.nx, 9), g.reshape(self.ny, self.nx, 9)
+
+    def nusselt(self, side: int = 0) -> float:
+        v = C.c_double()
+        rc = self.lib.orc_nusselt(self.h, int(side), C.byref(v))
+        if rc != 0:
+            raise OracleError("orc_nusselt: side is not a Dirichlet wall with a temperature difference")
+        return v.value
+
+    def totals(self):
+        vals = [C.c_double() for _ in range(4)]
+        self.lib.orc_totals(self.h, *[C.byref(v) for v in vals])
+        return tuple(v.value for v in vals)
+
+    def derived(self) -> dict:
+        d = Derived()
+        self.lib.orc_get_derived(self.h, C.byref(d))
+        return {n: getattr(d, n) for n, _ in Derived._fields_}
+
+    # ---- node-level building blocks ----
+    def pressure(self, rho, T):
+        return self.lib.orc_pressure(self.h, rho, T)
+
+    def meq(self, rho, ux, uy, eta):
+        o = _vec(9); self.lib.orc_meq(self.h, rho, ux, uy, eta, _ptr(o)); return o
+
+    def fm(self, fx, fy, ux, uy):
+        o = _vec(9); self.lib.orc_fm(self.h, fx, fy, ux, uy, _ptr(o)); return o
+
+    def neq(self, rho, rhoE, ux, uy, H, T):
+        o = _vec(9); self.lib.orc_neq(self.h, rho, rhoE, ux, uy, H, T, _ptr(o)); return o
+
+    def qm(self, qe, ux, uy):
+        o = _vec(9); self.lib.orc_qm(self.h, qe, ux, uy, _ptr(o)); return o
+
+    def rates(self, rho, T):
+        o = _vec(10); self.lib.orc_rates(self.h, rho, T, _ptr(o)); return o
+
+    def matrices(self, rho, ux, uy, T):
+        S, R, L, Y = (_vec(81) for _ in range(4))
+        Tm, X = _vec(18), _vec(18)
+        self.lib.orc_matrices(self.h, rho, ux, uy, T, *[_ptr(a) for a in (S, R, Tm, X, L, Y)])
+        return dict(S=S.reshape(9, 9), R=R.reshape(9, 9), T=Tm.reshape(9, 2), X=X.reshape(9, 2),
+                    L=L.reshape(9, 9), Y=Y.reshape(9, 9))
+
+    def collide_node(self, f, g, grad):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        grad = np.ascontiguousarray(grad, dtype=np.float64)
+        fb, gb, m, mb, n, nb = (_vec(9) for _ in range(6))
+        self.lib.orc_collide_node(self.h, _ptr(f), _ptr(g), _ptr(grad),
+                                  *[_ptr(a) for a in (fb, gb, m, mb, n, nb)])
+        return dict(fbar=fb, gbar=gb, m=m, mbar=mb, n=n, nbar=nb)
+
+
+def lattice():
+    lib = _load()
+    ex, ey = (C.c_int * 9)(), (C.c_int * 9)()
+    w = _vec(9)
+    lib.orc_lattice(ex, ey, _ptr(w))
+    return np.array(list(ex)), np.array(list(ey)), w
+
+
+def moment_matrix():
+    lib = _load()
+    M, Minv = _vec(81), _vec(81)
+    lib.orc_moment_matrix(_ptr(M), _ptr(Minv))
+    return M.reshape(9, 9), Minv.reshape(9, 9)

@@ -1,0 +1,273 @@
+"""Whole-step pins of the CPU oracle (no GPU): closed forms, invariants and
+the paper's own qualitative findings.  Sizes are chosen so that the suite
+runs in about a minute."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_08683_amd import inputs
+
+P = inputs._periodic
+W = inputs._side
+
+
+def _closed_cavity(N=12, eps=0.3, seed=None):
+    c = inputs.cavity(N=N, Ra=1e3, eps=eps, prec="f64")
+    c["nu0"] = 0.1
+    c["force"] = (0.0, -1e-4)
+    return c
+
+
+def test_quiescent_state_is_a_fixed_point():
+    """Rest at rho0, T0 with walls at T0 and no force stays at rest (the start
+    state of Secs. 4.1-4.3): the DFs change only by rounding."""
+    c = inputs.cavity(N=12, Ra=1e3, eps=0.1, prec="f64")
+    c["force"] = (0.0, 0.0)
+    c["nu0"] = 0.1
+    for s in c["sides"][:2]:
+        s["T"] = 1.0
+    o = oracle.Oracle(c).init()
+    f0, g0 = o.df()
+    o.step(200)
+    f1, g1 = o.df()
+    assert np.abs(f1 - f0).max() < 1e-13
+    assert np.abs(g1 - g0).max() < 1e-13
+    m = o.macros()
+    assert np.abs(m["ux"]).max() < 1e-13 and np.abs(m["T"] - 1).max() < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["cavity", "channel"])
+def test_mass_is_conserved(kind):
+    """Streaming with bounce-back temporaries permutes DFs, the collision keeps
+    sum_q f at each node and the wall rebuild keeps rho_b (Sec. 3), so the
+    total mass of a closed cavity or a periodic channel never changes."""
+    if kind == "cavity":
+        c = _closed_cavity()
+    else:
+        c = inputs.poiseuille(nx=5, ny=12, U0=0.05, nu=0.1, eos="ideal")
+        c["sides"][3]["T"] = 1.05
+    fields = inputs.random_fields(c, 4, du=0.01, drho=0.02, dT=0.02)
+    o = oracle.Oracle(c).init(**fields)
+    m0 = o.totals()[0]
+    o.step(300)
+    assert abs(o.totals()[0] - m0) / m0 < 1e-13
+
+
+def test_wall_nodes_satisfy_defining_equations():
+    """Sec. 3 (eq. decompose and the text around eqs. BB.f, BB.g): after the
+    rebuild the defining equations hold exactly at every wall node:
+    sum f = rho_b, sum e f + F/2 = rho_b u_b, sum g + q_e/2 = rho_b E_b."""
+    c = inputs.couette(nx=4, ny=12, U=0.05, T_bottom=1.0, T_top=1.03)
+    c["force"] = (2e-5, -3e-5)
+    c["per_mass"] = True
+    c["sides"][2]["thermal"] = "adiabatic"
+    o = oracle.Oracle(c).init(**inputs.random_fields(c, 8, du=0.01, drho=0.02, dT=0.02))
+    o.step(25)
+    f, g = o.df()
+    m = o.macros()
+    ex, ey, _ = oracle.lattice()
+    cv = o.derived()["cv"]
+    for y in (0, c["ny"] - 1):
+        for x in range(c["nx"]):
+            rho, ux, uy, T = m["rho"][y, x], m["ux"][y, x], m["uy"][y, x], m["T"][y, x]
+            Fx, Fy = rho * 2e-5, rho * -3e-5
+            assert f[y, x].sum() == pytest.approx(rho, rel=1e-14)
+            assert (ex * f[y, x]).sum() + Fx / 2 == pytest.approx(rho * ux, abs=1e-14)
+            assert (ey * f[y, x]).sum() + Fy / 2 == pytest.approx(rho * uy, abs=1e-14)
+            qe = ux * Fx + uy * Fy
+            E = cv * T + 0.5 * (ux * ux + uy * uy)
+            assert g[y, x].sum() + qe / 2 == pytest.approx(rho * E, rel=1e-13)
+    # prescribed wall values
+    assert np.allclose(m["ux"][-1], 0.05, atol=0) and np.allclose(m["T"][-1], 1.03, atol=0)
+    assert np.allclose(m["ux"][0], 0.0, atol=0)
+
+
+def test_shear_wave_decay_rate():
+    """eq. NSE: a shear wave u_x = U sin(k y) decays at nu k^2 with
+    nu = c_s^2 (1/s_p - 1/2) (decoupled EOS, periodic box)."""
+    N, nu = 32, 0.05
+    c = inputs.base_case(nx=4, ny=N, nu0=nu, eos="decoupled")
+    y = np.arange(N)[:, None] * np.ones((1, 4))
+    o = oracle.Oracle(c).init(ux=1e-4 * np.sin(2 * np.pi * y / N))
+    o.step(200)
+    a1 = np.abs(o.macros()["ux"]).max()
+    o.step(1000)
+    a2 = np.abs(o.macros()["ux"]).max()
+    k = 2 * np.pi / N
+    rate = -np.log(a2 / a1) / 1000
+    assert rate == pytest.approx(nu * k * k, rel=5e-3)
+
+
+def test_thermal_wave_decay_rate():
+    """eq. ECE.LBE with u = 0 and the decoupled EOS: a temperature wave decays
+    at lambda k^2 / (rho0 C_v) with lambda = kappa rho0 C_p (1/sigma_j - 1/2)."""
+    N, nu = 32, 0.05
+    c = inputs.base_case(nx=4, ny=N, nu0=nu, eos="decoupled")
+    y = np.arange(N)[:, None] * np.ones((1, 4))
+    o = oracle.Oracle(c).init(T=1 + 1e-3 * np.sin(2 * np.pi * y / N))
+    o.step(200)
+    a1 = np.abs(o.macros()["T"] - 1).max()
+    o.step(1000)
+    a2 = np.abs(o.macros()["T"] - 1).max()
+    k = 2 * np.pi / N
+    # lambda = C_p mu / Pr, so the decay is gamma * nu / Pr * k^2 at rho = rho0
+    expect = 1.4 * nu / 0.71 * k * k
+    assert -np.log(a2 / a1) / 1000 == pytest.approx(expect, rel=5e-3)
+
+
+def _standing_wave(c, N, steps, T_amp=0.0):
+    x = np.arange(N)[None, :] * np.ones((2, 1))
+    k = 2 * np.pi / N
+    o = oracle.Oracle(c).init(rho=1 + 1e-5 * np.cos(k * x),
+                              T=None if T_amp == 0 else 1 + T_amp * np.cos(k * x))
+    amp = []
+    cosk = np.cos(k * np.arange(N))
+    for _ in range(steps):
+        o.step(1)
+        amp.append(np.sum((o.macros()["rho"][0] - 1) * cosk) * 2 / N)
+    amp = np.array(amp)
+    s = np.sign(amp)
+    zc = np.where(s[:-1] * s[1:] < 0)[0]
+    period = 2 * np.mean(np.diff(zc))
+    pk = [i for i in range(1, len(amp) - 1) if abs(amp[i]) >= abs(amp[i - 1]) and abs(amp[i]) >= abs(amp[i + 1])]
+    rate = -np.polyfit(np.array(pk), np.log(np.abs(amp[pk])), 1)[0]
+    return 2 * np.pi / period / k, rate, k
+
+
+def test_sound_wave_isothermal_speed_and_bulk_viscosity():
+    """eq. NSE with the decoupled EOS: sound travels at c_s = 1/sqrt(3) and
+    decays at (nu + bulk) k^2 / 2 with bulk = varpi c_s^2 (1/s_e - 1/2)."""
+    N, nu = 64, 0.02
+    c = inputs.base_case(nx=N, ny=2, nu0=nu, eos="decoupled", bulk_ratio=1.0)
+    speed, rate, k = _standing_wave(c, N, 900)
+    assert speed == pytest.approx(np.sqrt(1 / 3), rel=3e-3)
+    assert rate == pytest.approx((nu + nu) * k * k / 2, rel=3e-2)
+
+
+def test_sound_wave_adiabatic_speed_with_ideal_gas():
+    """With the ideal-gas EOS the self-tuning EOS (eta from p_EOS(rho, T)) and
+    the compression work carried by H = E + p/rho make sound adiabatic:
+    speed sqrt(gamma R T0) (Sec. 2.2), attenuation (nu + bulk + (gamma-1)
+    lambda/(rho C_p)) k^2 / 2 (viscous plus conduction damping)."""
+    N, nu = 64, 0.1
+    c = inputs.base_case(nx=N, ny=2, nu0=nu, eos="ideal", bulk_ratio=1.0)
+    speed, rate, k = _standing_wave(c, N, 700, T_amp=1e-5 * 0.4)
+    assert speed == pytest.approx(np.sqrt(1.4 / 3), rel=3e-3)
+    alpha = nu / 0.71
+    assert rate == pytest.approx((2 * nu + 0.4 * alpha) * k * k / 2, rel=6e-2)
+
+
+def test_steady_conduction_is_linear():
+    """Decoupled EOS, Dirichlet walls, no flow: the steady temperature solves
+    lambda T'' = 0; with second-order extrapolation (eq. neq.extrapolation) the
+    profile is linear to rounding."""
+    c = inputs.base_case(nx=3, ny=17, nu0=0.1, eos="decoupled",
+                         sides=[P(), P(), W(T=1.05), W(T=0.95)], extrap_order=2)
+    o = oracle.Oracle(c).init()
+    o.step(20000)
+    T = o.macros()["T"][:, 0]
+    assert np.abs(T - (1.05 - 0.1 * np.arange(17) / 16)).max() < 1e-12
+
+
+def test_heated_couette_profiles():
+    """Steady heated Couette flow (constant mu and lambda, ideal gas):
+    u = U y/W, T = T_b + (T_t - T_b) y/W + (Pr U^2 / (2 C_p)) (y/W)(1 - y/W),
+    p uniform so rho ~ 1/T with the initial mass.  The viscous-heating bump
+    exists only through the Y coupling of eq. LBE.T.c."""
+    ny, U = 33, 0.05
+    c = inputs.couette(nx=3, ny=ny, U=U)
+    o = oracle.Oracle(c).init()
+    o.step(40000)
+    m = o.macros()
+    yy = np.arange(ny) / (ny - 1)
+    cp, Pr = 3.5 / 3, 0.71
+    ux, T, rho = m["ux"][:, 0], m["T"][:, 0], m["rho"][:, 0]
+    u_an = U * yy
+    bump_an = Pr * U * U / (2 * cp) * yy * (1 - yy)
+    T_an = 1.0 + 0.02 * yy + bump_an
+    assert np.sqrt(((ux - u_an) ** 2).sum() / (u_an ** 2).sum()) < 5e-4
+    bump = T - (1.0 + 0.02 * yy)
+    assert np.abs(bump - bump_an).max() < 0.01 * bump_an.max()
+    rho_an = ny / np.sum(1 / T_an) / T_an
+    assert np.abs(rho / rho_an - 1).max() < 1e-6
+
+
+def _vdw_density(p, T, R, a, b):
+    r = np.ones_like(T)
+    for _ in range(60):
+        fn = r * R * T / (1 - b * r) - a * r * r - p
+        dfn = R * T / (1 - b * r) ** 2 - 2 * a * r
+        r = r - fn / dfn
+    return r
+
+
+def test_poiseuille_with_van_der_waals():
+    """eq. Poiseuille.u.T with T_h = T_c: parabolic u and the quartic viscous
+    heating Pr U0^2/(3 C_p) [1 - (1 - 2y/W)^4]; density from p uniform in the
+    van der Waals EOS with the initial mass (the analogue of eq. rho.analytical
+    for a fourth EOS)."""
+    ny, U0 = 33, 0.05
+    c = inputs.poiseuille(nx=3, ny=ny, U0=U0, nu=0.1)
+    o = oracle.Oracle(c).init()
+    o.step(60000)
+    m = o.macros()
+    d = o.derived()
+    yy = np.arange(ny) / (ny - 1)
+    u_an = 4 * U0 * yy * (1 - yy)
+    dT = 0.71 * U0 ** 2 / (3 * d["cp"]) * (1 - (1 - 2 * yy) ** 4)
+    ux, T, rho = m["ux"][:, 0], m["T"][:, 0], m["rho"][:, 0]
+    assert np.sqrt(((ux - u_an) ** 2).sum() / (u_an ** 2).sum()) < 1e-3
+    assert np.abs((T - 1) - dT).max() < 0.05 * dT.max()
+    p = 0.0
+    lo, hi = 0.2, 0.5
+    for _ in range(200):     # bisection on the uniform pressure
+        p = 0.5 * (lo + hi)
+        if _vdw_density(p, 1 + dT, d["R"], 0.05, 0.2).sum() > ny:
+            hi = p
+        else:
+            lo = p
+    rho_an = _vdw_density(p, 1 + dT, d["R"], 0.05, 0.2)
+    assert np.abs(rho / rho_an - 1).max() < 2e-4
+
+
+@pytest.mark.parametrize("eos,unstable", [("ideal", True), ("decoupled", False), ("cs", False)])
+def test_paper_unstable_poiseuille_set(eos, unstable, golden):
+    """Sec. 4.1: at tau = 0.8, Ma = 0.2, Ec = 10, Pr = 0.1 the ideal-gas run
+    loses stability while the other EOSs do not."""
+    ref = golden["unstable_sets"]["poiseuille"]
+    U0 = ref["Ma_lattice"] * np.sqrt(1 / 3)
+    dTw = U0 ** 2 / ((3.5 / 3) * ref["Ec"])
+    c = inputs.poiseuille(nx=3, ny=33, U0=U0, nu=(ref["tau"] - 0.5) / 3, eos=eos, a=0.0, b=0.0)
+    c["Pr"] = ref["Pr"]
+    c["sides"][3]["T"] = 1.0 + dTw
+    if eos == "cs":
+        c["cv_rule"] = 1
+    o = oracle.Oracle(c).init()
+    if unstable:
+        with pytest.raises(oracle.OracleError, match="diverged"):
+            o.step(5000)
+    else:
+        o.step(5000)
+        assert np.isfinite(o.macros()["T"]).all()
+
+
+def test_divergence_is_reported():
+    """A run that blows up reports divergence instead of returning garbage."""
+    c = inputs.base_case(nx=8, ny=8, nu0=0.0005, eos="ideal")
+    fields = inputs.random_fields(c, 2, du=0.2, drho=0.3, dT=0.3)
+    o = oracle.Oracle(c).init(**fields)
+    with pytest.raises(oracle.OracleError):
+        o.step(2000)
+
+
+def test_nusselt_of_pure_conduction():
+    """Nu = 1 for steady conduction between Dirichlet walls (Sec. 4.3 Nu
+    definition, no gravity, decoupled EOS keeps the gas at rest)."""
+    N = 12
+    c = inputs.base_case(nx=N, ny=N, nu0=0.1, eos="decoupled",
+                         sides=[W(T=1.05), W(T=0.95), W(thermal="adiabatic"), W(thermal="adiabatic")],
+                         extrap_order=2)
+    o = oracle.Oracle(c).init()
+    o.step(8000)
+    assert o.nusselt(0) == pytest.approx(1.0, abs=1e-6)
+    assert o.nusselt(1) == pytest.approx(1.0, abs=1e-6)
