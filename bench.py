@@ -1,0 +1,161 @@
+"""Benchmark of the coupled f+g D2Q9 MRT step on one MI355X.
+
+Workload: the differentially heated cavity of Sec. 4.3 at 2048 x 2048 nodes,
+eps = 0.6, Ra = 1e8, Pr = 0.71, gamma = 1.4, Sutherland viscosity, tau0 = 0.8,
+first-order wall extrapolation, all cubic corrections on; synthetic state
+(rest + 1e-6 density noise from splitmix64 seed 1), resident in HBM before
+the timed region.  One step = one fused launch that streams and collides both
+DFs of every node, walls included.
+
+Headline value: FP32-storage MLUPS (million node updates per second).  The
+FP16-offset and FP64 paths are timed on the same workload and reported under
+"paths".  Roofline: algorithmic HBM bytes per node and step = 2 DFs x 9
+values x (read + write) x bytes per value, over the average kernel time
+measured with HIP events on the launch stream, against 8 TB/s.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled f+g MLUPS and % of HBM roofline, 2048² cavity, FP32/FP16 vs FP64"
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_NODE = {"f64": 288, "f32": 144, "f16s": 72}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_path(case, prec, steps, warmup, seg_rows=0):
+    import torch
+    from paper_1809_08683_amd import lbm
+
+    c = dict(case, prec=prec)
+    stream = torch.cuda.Stream()
+    ctx = lbm.Context(c, stream=stream, seg_rows=seg_rows)
+    ctx.init(**c["init"])
+    if warmup:
+        ctx.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kernel_ms = ctx.step_timed(steps)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    nodes = c["nx"] * c["ny"]
+    per_step_kernel_s = kernel_ms * 1e-3 / steps
+    res = {
+        "mlups": nodes * steps / wall_s / 1e6,
+        "ms_per_step": wall_s * 1e3 / steps,
+        "kernel_ms_per_step": per_step_kernel_s * 1e3,
+        "kernel_mlups": nodes / per_step_kernel_s / 1e6,
+        "bytes_per_node": BYTES_PER_NODE[prec],
+        "achieved_GBs": BYTES_PER_NODE[prec] * nodes / per_step_kernel_s / 1e9,
+        "work_items": ctx.work_items,
+    }
+    res["frac_hbm"] = res["achieved_GBs"] / PEAK_HBM_GBS
+    ctx.close()
+    return res
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 CPU oracle (single thread, as written) on a bounded sample:
+    a 256 x 256 cavity (eps 0.6, Ra 1e5) stepped until ~15 s have passed."""
+    import oracle
+    from paper_1809_08683_amd import inputs
+
+    c = inputs.cavity(N=256, Ra=1e5, prec="f64", noise_seed=1)
+    o = oracle.Oracle(c).init(**c["init"])
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds_target:
+        o.step(5)
+        steps += 5
+    dt = time.perf_counter() - t0
+    return {"value": 256 * 256 * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"256x256 cavity (eps 0.6, Ra 1e5), {steps} steps, FP64, one host thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--paths", default="f32,f16s,f64")
+    ap.add_argument("--seg-rows", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU slab decomposition is "
+              "described in DESIGN.md but not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1809_08683_amd import inputs, lbm
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    lbm.load_library()
+
+    case = inputs.cavity(N=args.n, Ra=1e8, eps=0.6, prec="f32", noise_seed=1)
+    paths = {}
+    for prec in args.paths.split(","):
+        log(f"bench: {args.n}^2 cavity {prec}: warmup {args.warmup}, timed {args.steps} steps")
+        paths[prec] = time_path(case, prec, args.steps, args.warmup, args.seg_rows)
+        log(f"bench: {prec}: {json.dumps(paths[prec])}")
+    copy_gbs, _ = lbm.copy_bandwidth(1 << 30, iters=20)
+    log(f"bench: device copy bandwidth {copy_gbs:.0f} GB/s")
+
+    head = "f32" if "f32" in paths else list(paths)[0]
+    h = paths[head]
+    out = {
+        "metric": METRIC,
+        "value": round(h["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(h["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {
+            "workload": f"differentially heated cavity {args.n}x{args.n}, eps 0.6, Ra 1e8, Pr 0.71, "
+                        f"gamma 1.4, Sutherland, tau0 0.8, bulk/shear 4, 1st-order walls, "
+                        f"cubic corrections on, {head} storage",
+            "nx": args.n, "ny": args.n, "prec": head,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(h["achieved_GBs"], 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(h["frac_hbm"], 4),
+            "traffic": None,
+        },
+        "paths": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                  for k, v in paths.items()},
+        "copy_bandwidth_GBs": round(copy_gbs, 1),
+    }
+    if "f64" in paths:
+        out["speedup_vs_f64"] = {k: round(v["mlups"] / paths["f64"]["mlups"], 3) for k, v in paths.items()}
+    if not args.no_cpu:
+        log("bench: cpu_baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

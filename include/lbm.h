@@ -1,0 +1,204 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) implementation of the coupled
+ * density / total-energy D2Q9 MRT lattice Boltzmann step of
+ * R. Huang, H. Wu, N. A. Adams, "Lattice Boltzmann model with self-tuning
+ * equation of state for coupled thermo-hydrodynamic flows" (arXiv:1809.08683).
+ *
+ * One time step (lbm_step) is the fused streaming + collision of both DFs:
+ *   - density DF f: eq. LBE.u (Sec. 2.1): MRT collision with the self-tuning
+ *     EOS (eta from p_EOS), force moments F_m, non-diagonal S and the cubic
+ *     corrections R, T.grad(rho), X.grad(p);
+ *   - total-energy DF g: eq. LBE.T (Sec. 2.2, App. C): MRT collision with
+ *     the modified L and the density-DF coupling Y((m + mbar)/2 - m^eq);
+ *   - walls (Sec. 3, App. B): bounce-back temporaries for the wall macros,
+ *     then every DF of a wall node rebuilt from equilibrium, force and the
+ *     extrapolated tilde non-equilibrium parts.
+ *
+ * Conventions
+ *   - Lattice units: dx = dt = c = 1, c_s^2 = 1/3.
+ *   - Grid: nx * ny nodes, node (x, y) at host index y*nx + x (x fastest).
+ *     Walls sit on the boundary nodes (Sec. 3.1): a wall side's nodes are
+ *     the first/last column or row.  Sides: 0 = {x = 0}, 1 = {x = nx-1},
+ *     2 = {y = 0}, 3 = {y = ny-1}; opposite sides are both walls or both
+ *     periodic.  A walled axis needs at least 5 nodes.
+ *   - Host arrays are caller-owned, FP64, nx*ny long; the library never keeps
+ *     a caller pointer.  A NULL output pointer means "skip".
+ *   - Device memory is owned by the context (hipMalloc), or supplied by the
+ *     caller through lbm_create_ex (it must stay valid until lbm_destroy).
+ *   - Time: lbm_init sets t = 0; lbm_step(n) advances t by n.  lbm_macros,
+ *     lbm_nusselt and lbm_totals report the pre-collision macroscopic state
+ *     at the current t (wall nodes report their prescribed/derived values).
+ *   - Every call returns an lbm_status; lbm_last_error gives details.
+ *     LBM_EDIVERGED (non-finite or non-positive rho or T seen at the end of
+ *     a step call) leaves the state readable.
+ *   - One context per host thread; calls on one context are not reentrant.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument; nothing changed */
+    LBM_ENOMEM = -2,     /* device allocation failed / workspace too small */
+    LBM_EDEVICE = -3,    /* HIP runtime error */
+    LBM_EDIVERGED = -4,  /* state contains non-finite or non-positive rho/T */
+    LBM_ESTATE = -5      /* call out of order (e.g. step before init) */
+} lbm_status;
+
+/* Equations of state (Sec. 4, eqs. EOSs; van der Waals added):
+ *   DECOUPLED p = rho R T0, IDEAL p = rho R T,
+ *   VDW p = rho R T / (1 - b rho) - a rho^2,
+ *   CS  p = Z rho R T, Z = (1 + y + y^2 - y^3)/(1 - y)^3, y = b rho / 4,
+ *       b <= 0 selecting sqrt(2) pi / (3 rho0).
+ * R <= 0 selects the R for which dp/drho at (rho0, T0) equals c_s^2
+ * (eq. cs). */
+typedef enum { LBM_EOS_DECOUPLED = 0, LBM_EOS_IDEAL = 1, LBM_EOS_VDW = 2, LBM_EOS_CS = 3 } lbm_eos_kind;
+typedef struct {
+    int kind;            /* lbm_eos_kind */
+    double R, rho0, T0, a, b;
+} lbm_eos;
+
+/* Viscosity law mu(T): constant, mu0 T/T0, or Sutherland's law referred to
+ * (T0, mu0) with constant S (in units of T0) (Sec. 4.3). */
+typedef enum { LBM_VISC_CONST = 0, LBM_VISC_LINEAR = 1, LBM_VISC_SUTHERLAND = 2 } lbm_visc_law;
+
+/* Relaxation (Sec. 4): the local rates follow from
+ *   nu = mu(T)/rho = c_s^2 (1/s_p - 1/2),  (1/s_p - 1/2)(1/s_q - 1/2) = 1/12,
+ *   bulk viscosity varpi c_s^2 (1/s_e - 1/2) = bulk_ratio * nu, s_eps = s_e,
+ *   s_0 = s_j = 1;  lambda = C_p mu / Pr = kappa rho0 C_p (1/sigma_j - 1/2),
+ *   (1/sigma_j - 1/2)(1/sigma_e - 1/2) = 1/4, sigma_eps = sigma_p = sigma_e,
+ *   sigma_q = sigma_j, sigma_0 = 1;  varpi = 1/6, gamma1 = -2, gamma2 = 2. */
+typedef struct {
+    double nu0;          /* mu0 / rho0 at T0; tau0 = 3 nu0 + 1/2 */
+    double bulk_ratio;   /* bulk / kinematic viscosity (Table 1: 1, 2 or 4) */
+    int law;             /* lbm_visc_law */
+    double sutherland_S; /* S / T0 */
+} lbm_relax;
+
+typedef struct {
+    int wall;            /* 1: wall side, 0: periodic */
+    double ux, uy;       /* wall velocity (no-slip value, Sec. 3.1) */
+    int adiabatic;       /* 1: zero heat flux, 0: Dirichlet temperature T */
+    double T;
+} lbm_side;
+
+typedef struct {
+    lbm_side side[4];
+    int extrap_order;    /* 1 or 2 (eq. neq.extrapolation) */
+} lbm_boundary;
+
+/* Storage precision of the DFs:
+ *   FP64  - FP64 storage and arithmetic;
+ *   FP32  - FP32 storage and arithmetic, temperature recovered in FP64;
+ *   FP16S - FP16 storage of the offsets from the rest-state equilibrium,
+ *           FP32 arithmetic, temperature recovered in FP64. */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 } lbm_precision;
+
+typedef struct {
+    double fx, fy;       /* force per unit volume, or per unit mass if per_mass */
+    int per_mass;        /* 1: F = rho (fx, fy) (gravity) */
+    int prec;            /* lbm_precision */
+    int cubic;           /* 0: no R, T, X; 1: R only; 2: R, T and X (default) */
+    double cp;           /* <= 0: C_p = 3.5 c_s^2 / T0 (eq. Cp) */
+    int cv_rule;         /* 0: C_v = C_p / gamma; 1: C_v = C_p - p(rho0,T0)/(rho0 T0) */
+    int seg_rows;        /* rows per interior work item (0: automatic) */
+    void* hip_stream;    /* hipStream_t to launch on; NULL: context-owned stream */
+} lbm_options;
+
+/* Create a context.  Validates the parameters (positive sizes, walled axes
+ * >= 5 nodes, rho0, T0, Pr, gamma, nu0 > 0, 0 < s_p, sigma_j < 2 at the
+ * reference state) and allocates device memory. */
+lbm_status lbm_create(int nx, int ny, const lbm_eos* eos, double Pr, double gamma,
+                      const lbm_relax* relax, const lbm_boundary* bc,
+                      const lbm_options* opt, lbm_ctx** out);
+
+/* Device bytes lbm_create_ex needs for one case. */
+size_t lbm_workspace_bytes(int nx, int ny, int prec);
+
+/* As lbm_create, but places all per-case device arrays in the caller's
+ * device allocation [dev_workspace, dev_workspace + bytes) (e.g. a torch
+ * tensor); LBM_ENOMEM if bytes < lbm_workspace_bytes(nx, ny, prec). */
+lbm_status lbm_create_ex(int nx, int ny, const lbm_eos* eos, double Pr, double gamma,
+                         const lbm_relax* relax, const lbm_boundary* bc,
+                         const lbm_options* opt, void* dev_workspace, size_t bytes,
+                         lbm_ctx** out);
+
+/* Initial state (t = 0) from host macroscopic fields: at every node, walls
+ * included, m = m^eq - F_m/2 and n = n^eq - Q_m/2 (zero non-equilibrium
+ * part), with E = C_v T + |u|^2/2.  NULL fields mean rho0, 0, 0, T0.
+ * Synchronises the stream. */
+lbm_status lbm_init(lbm_ctx* ctx, const double* rho, const double* ux,
+                    const double* uy, const double* T);
+
+/* Advance n >= 0 time steps (one kernel launch per step, on the context
+ * stream), then check the state for divergence (synchronises). */
+lbm_status lbm_step(lbm_ctx* ctx, long long n);
+
+/* As lbm_step, and report the elapsed device time of the n steps measured
+ * with HIP events on the context stream (milliseconds). */
+lbm_status lbm_step_timed(lbm_ctx* ctx, long long n, double* ms);
+
+/* Macroscopic fields at the current time (FP64 host arrays, nx*ny). */
+lbm_status lbm_macros(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* T, double* p);
+
+/* Mean Nusselt number through Dirichlet side `side` (Sec. 4.3):
+ * Nu = (1/(lambda0 (T_lo - T_hi))) * sum_j w_j (-lambda(T) dT/dn),
+ * n the side's axis (+x or +y), T_lo/T_hi the Dirichlet values of the two
+ * sides of that axis, a second-order one-sided dT/dn, trapezoid weights w_j.
+ * FP64 on the device.  LBM_EINVAL if the side or its opposite is not a
+ * Dirichlet wall or T_lo == T_hi. */
+lbm_status lbm_nusselt(lbm_ctx* ctx, int side, double* nu);
+
+/* Sums over all nodes of rho, rho ux, rho uy and rho E (FP64 on the device,
+ * fixed reduction order). */
+lbm_status lbm_totals(lbm_ctx* ctx, double* mass, double* momx, double* momy, double* energy);
+
+/* Checkpoint: raw DF state plus time; bytes = lbm_state_bytes(ctx). */
+size_t     lbm_state_bytes(const lbm_ctx* ctx);
+lbm_status lbm_save(lbm_ctx* ctx, void* host, size_t bytes);
+lbm_status lbm_load(lbm_ctx* ctx, const void* host, size_t bytes);
+
+long long   lbm_time(const lbm_ctx* ctx);
+const char* lbm_last_error(const lbm_ctx* ctx);
+void        lbm_destroy(lbm_ctx* ctx);
+
+/* ---- batches of independent cases stepped by one launch per step ----
+ * Every pointer argument is an array of ncases entries; all cases share
+ * opt[0].prec and opt[0].hip_stream. */
+lbm_status lbm_batch_create(int ncases, const int* nx, const int* ny, const lbm_eos* eos,
+                            const double* Pr, const double* gamma, const lbm_relax* relax,
+                            const lbm_boundary* bc, const lbm_options* opt, lbm_ctx** out);
+int        lbm_batch_size(const lbm_ctx* ctx);
+/* Per-case variants of lbm_init / lbm_macros / lbm_nusselt / lbm_totals. */
+lbm_status lbm_case_init(lbm_ctx* ctx, int case_id, const double* rho, const double* ux,
+                         const double* uy, const double* T);
+lbm_status lbm_case_macros(lbm_ctx* ctx, int case_id, double* rho, double* ux, double* uy,
+                           double* T, double* p);
+lbm_status lbm_case_nusselt(lbm_ctx* ctx, int case_id, int side, double* nu);
+lbm_status lbm_case_totals(lbm_ctx* ctx, int case_id, double* mass, double* momx, double* momy,
+                           double* energy);
+/* Divergence flag of each case (1: diverged) after the last step call. */
+lbm_status lbm_batch_flags(lbm_ctx* ctx, int* diverged);
+
+/* Number of work items one step launches (for roofline accounting). */
+long long  lbm_work_items(const lbm_ctx* ctx);
+
+/* Plain device copy of `bytes` (multiple of 16) repeated `iters` times on
+ * `hip_stream` (NULL: default stream) with library-owned buffers; reports
+ * the copy bandwidth 2 * bytes / time (GB/s) and the time per copy (ms).
+ * Used as the measured-bandwidth reference of the roofline and to calibrate
+ * hardware byte counters. */
+lbm_status lbm_copy_bandwidth(size_t bytes, int iters, void* hip_stream, double* gbps, double* ms_per_copy);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

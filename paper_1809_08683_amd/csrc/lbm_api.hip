@@ -1,0 +1,662 @@
+// Host runtime and C ABI (include/lbm.h) of the gfx950 lattice Boltzmann
+// library: parameter validation and derived constants, device memory, the
+// per-step work list, launches, reductions and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_params.hpp"
+
+namespace lbm {
+int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
+                int export_macros, hipStream_t stream);
+int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
+                int parity, hipStream_t stream);
+int launch_totals(const CaseParams* d_cases, int case_id, double* d_partial, int nblocks, double* d_out,
+                  hipStream_t stream);
+int launch_nusselt(const CaseParams* d_cases, int case_id, int side, double* d_out, hipStream_t stream);
+int launch_copy(const void* src, void* dst, long long bytes, hipStream_t stream);
+}  // namespace lbm
+
+namespace {
+
+constexpr double kCs2 = 1.0 / 3.0;
+// model constants of Sec. 4 used on the host side (rest state, kappa)
+constexpr double kVarpi = 1.0 / 6.0, kGamma1 = -2.0, kGamma2 = 2.0;
+constexpr double kKappa = 2.0 / 3.0 + kGamma1 / 2.0 + kGamma2 / 3.0;
+constexpr int kAlignElems = 32;      // stored rows start on 32-element boundaries
+constexpr int kRedBlocks = 240;
+
+size_t elem_size(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    int pitch;
+    long long plane;
+    size_t buf_bytes, macro_bytes, flag_bytes, total;
+};
+
+Layout layout_of(int nx, int ny, int prec)
+{
+    Layout L;
+    L.pitch = int(round_up(size_t(nx) + 2, kAlignElems));
+    L.plane = (long long)(ny + 2) * L.pitch;
+    const size_t es = elem_size(prec);
+    L.buf_bytes = round_up((size_t(18) * L.plane + kAlignElems) * es, 256);
+    L.macro_bytes = round_up(size_t(5) * nx * ny * sizeof(double), 256);
+    L.flag_bytes = 256;
+    L.total = 2 * L.buf_bytes + L.macro_bytes + L.flag_bytes;
+    return L;
+}
+
+struct CaseHost {
+    int nx, ny;
+    Layout L;
+    char* base = nullptr;     // start of the case's device memory
+    bool inited = false;
+};
+
+}  // namespace
+
+struct lbm_ctx {
+    int prec = LBM_FP32;
+    std::vector<lbm::CaseParams> P;
+    std::vector<CaseHost> H;
+    lbm::CaseParams* d_P = nullptr;
+    std::vector<lbm::WorkItem> work;
+    lbm::WorkItem* d_work = nullptr;
+    double* d_red = nullptr;
+    std::vector<void*> allocs;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int parity = 0;
+    long long t = 0;
+    std::string err;
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx* c, lbm_status code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* where)
+{
+    return fail(c, LBM_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                             \
+    do {                                                               \
+        hipError_t e_ = (expr);                                        \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);       \
+    } while (0)
+
+// ---- thermodynamics of the case (Sec. 4) --------------------------------
+double cs_b_of(const lbm_eos& e) { return e.b > 0 ? e.b : std::sqrt(2.0) * M_PI / (3.0 * e.rho0); }
+
+double cs_Z(double y) { return (1 + y + y * y - y * y * y) / std::pow(1 - y, 3); }
+
+double pressure(const lbm_eos& e, double R, double rho, double T)
+{
+    switch (e.kind) {
+    case LBM_EOS_DECOUPLED: return rho * R * e.T0;
+    case LBM_EOS_IDEAL: return rho * R * T;
+    case LBM_EOS_VDW: return rho * R * T / (1 - e.b * rho) - e.a * rho * rho;
+    default: return cs_Z(cs_b_of(e) * rho / 4) * rho * R * T;
+    }
+}
+
+// R with dp/drho(rho0, T0) = c_s^2 (eq. cs)
+double gas_constant(const lbm_eos& e)
+{
+    if (e.R > 0) return e.R;
+    switch (e.kind) {
+    case LBM_EOS_DECOUPLED:
+    case LBM_EOS_IDEAL: return kCs2 / e.T0;
+    case LBM_EOS_VDW: return (kCs2 + 2 * e.a * e.rho0) * (1 - e.b * e.rho0) * (1 - e.b * e.rho0) / e.T0;
+    default: {
+        const double y = cs_b_of(e) * e.rho0 / 4;
+        const double dzdy = (4 + 4 * y - 2 * y * y) / std::pow(1 - y, 4);
+        return kCs2 / (e.T0 * (cs_Z(y) + y * dzdy));
+    }
+    }
+}
+
+template <typename C>
+void fill_coef(lbm::Coef<C>& K, const lbm_eos& e, double R, double cp, double cv, double Pr,
+               const lbm_relax& r, const lbm_options& o, const lbm_boundary& bc)
+{
+    K.rho0 = C(e.rho0);
+    K.T0 = C(e.T0);
+    K.inv_T0 = C(1.0 / e.T0);
+    K.R = C(R);
+    K.a_vdw = C(e.a);
+    K.b_vdw = C(e.b);
+    K.b_cs = C(cs_b_of(e));
+    K.rho0_cp = C(e.rho0 * cp);
+    K.mu0 = C(e.rho0 * r.nu0);
+    K.suth_S = C(r.sutherland_S);
+    K.suth_1pS = C(1.0 + r.sutherland_S);
+    K.bulk_over_varpi = C(r.bulk_ratio / kVarpi);
+    K.varpi_over_bulk = C(kVarpi / r.bulk_ratio);
+    K.inv_kappa_rho0_Pr = C(1.0 / (kKappa * e.rho0 * Pr));
+    K.kappa_rho0_Pr = C(kKappa * e.rho0 * Pr);
+    K.fx = C(o.fx);
+    K.fy = C(o.fy);
+    for (int s = 0; s < 4; ++s) {
+        K.side_ux[s] = C(bc.side[s].ux);
+        K.side_uy[s] = C(bc.side[s].uy);
+        K.side_T[s] = bc.side[s].T;
+    }
+    K.cv_d = cv;
+    K.inv_cv_d = 1.0 / cv;
+    K.rho0_d = e.rho0;
+    K.T0_d = e.T0;
+    K.p0_d = pressure(e, R, e.rho0, e.T0);
+    K.rhoE0_d = e.rho0 * cv * e.T0;
+    K.R_d = R;
+    K.a_d = e.a;
+    K.b_d = e.b;
+    K.bcs_d = cs_b_of(e);
+}
+
+lbm_status validate(lbm_ctx* c, int nx, int ny, const lbm_eos* eos, double Pr, double gamma,
+                    const lbm_relax* relax, const lbm_boundary* bc, const lbm_options* opt)
+{
+    if (!eos || !relax || !bc || !opt) return fail(c, LBM_EINVAL, "null parameter block");
+    if (nx < 1 || ny < 1) return fail(c, LBM_EINVAL, "grid size must be positive");
+    if ((long long)nx * ny > (1LL << 31) - 1) return fail(c, LBM_EINVAL, "grid too large");
+    if (bc->side[0].wall != bc->side[1].wall || bc->side[2].wall != bc->side[3].wall)
+        return fail(c, LBM_EINVAL, "opposite sides must both be walls or both periodic");
+    if ((bc->side[0].wall && nx < 5) || (bc->side[2].wall && ny < 5))
+        return fail(c, LBM_EINVAL, "a walled axis needs at least 5 nodes");
+    if (eos->kind < 0 || eos->kind > 3) return fail(c, LBM_EINVAL, "unknown EOS");
+    if (!(eos->rho0 > 0) || !(eos->T0 > 0)) return fail(c, LBM_EINVAL, "rho0 and T0 must be positive");
+    if (eos->kind == LBM_EOS_VDW && !(eos->b * eos->rho0 < 1)) return fail(c, LBM_EINVAL, "van der Waals b rho0 >= 1");
+    if (!(Pr > 0) || !(gamma > 0)) return fail(c, LBM_EINVAL, "Pr and gamma must be positive");
+    if (!(relax->nu0 > 0)) return fail(c, LBM_EINVAL, "nu0 must be positive");
+    if (!(relax->bulk_ratio > 0)) return fail(c, LBM_EINVAL, "bulk_ratio must be positive");
+    if (relax->law < 0 || relax->law > 2) return fail(c, LBM_EINVAL, "unknown viscosity law");
+    if (relax->law == LBM_VISC_SUTHERLAND && !(relax->sutherland_S >= 0))
+        return fail(c, LBM_EINVAL, "Sutherland S must be >= 0");
+    if (bc->extrap_order < 1 || bc->extrap_order > 2) return fail(c, LBM_EINVAL, "extrap_order must be 1 or 2");
+    if (opt->prec < 0 || opt->prec > 2) return fail(c, LBM_EINVAL, "unknown precision");
+    if (opt->cubic < 0 || opt->cubic > 2) return fail(c, LBM_EINVAL, "cubic must be 0, 1 or 2");
+    for (int s = 0; s < 4; ++s) {
+        const lbm_side& sd = bc->side[s];
+        if (!std::isfinite(sd.ux) || !std::isfinite(sd.uy)) return fail(c, LBM_EINVAL, "non-finite wall velocity");
+        if (sd.wall && !sd.adiabatic && !(sd.T > 0)) return fail(c, LBM_EINVAL, "wall temperature must be positive");
+    }
+    const double R = gas_constant(*eos);
+    if (!(R > 0) || !std::isfinite(R)) return fail(c, LBM_EINVAL, "equation of state gives no valid R");
+    const double cp = opt->cp > 0 ? opt->cp : 3.5 * kCs2 / eos->T0;
+    const double cv = opt->cv_rule ? cp - pressure(*eos, R, eos->rho0, eos->T0) / (eos->rho0 * eos->T0) : cp / gamma;
+    if (!(cv > 0)) return fail(c, LBM_EINVAL, "C_v must be positive");
+    return LBM_OK;
+}
+
+void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr, double gamma,
+                const lbm_relax& r, const lbm_boundary& bc, const lbm_options& o, const Layout& L,
+                char* base)
+{
+    std::memset(&P, 0, sizeof P);
+    P.nx = nx;
+    P.ny = ny;
+    P.pitch = L.pitch;
+    P.plane = L.plane;
+    P.wall_x = bc.side[0].wall ? 1 : 0;
+    P.wall_y = bc.side[2].wall ? 1 : 0;
+    P.eos = e.kind;
+    P.visc_law = r.law;
+    P.per_mass = o.per_mass ? 1 : 0;
+    P.cubic = o.cubic;
+    P.extrap_order = bc.extrap_order;
+    for (int s = 0; s < 4; ++s) P.side_adiabatic[s] = bc.side[s].adiabatic ? 1 : 0;
+    const size_t es = elem_size(o.prec);
+    // shift so that the first node of every stored row (column 1) is aligned
+    P.buf[0] = base + (kAlignElems - 1) * es;
+    P.buf[1] = base + L.buf_bytes + (kAlignElems - 1) * es;
+    P.macro = reinterpret_cast<double*>(base + 2 * L.buf_bytes);
+    P.flag = reinterpret_cast<int*>(base + 2 * L.buf_bytes + L.macro_bytes);
+
+    const double R = gas_constant(e);
+    const double cp = o.cp > 0 ? o.cp : 3.5 * kCs2 / e.T0;
+    const double cv = o.cv_rule ? cp - pressure(e, R, e.rho0, e.T0) / (e.rho0 * e.T0) : cp / gamma;
+    fill_coef<double>(P.cd, e, R, cp, cv, Pr, r, o, bc);
+    fill_coef<float>(P.cf, e, R, cp, cv, Pr, r, o, bc);
+
+}
+
+int auto_seg_rows(int rows, int strips)
+{
+    // about 4096 interior wavefronts per case at large sizes
+    long long per = (long long)rows * strips / 4096;
+    return int(std::max<long long>(4, std::min<long long>(64, per)));
+}
+
+void build_work(lbm_ctx* c, int seg_rows)
+{
+    c->work.clear();
+    const int nc = int(c->P.size());
+    for (int k = 0; k < nc; ++k) {
+        const auto& P = c->P[k];
+        int nw = 0;
+        if (P.wall_y) nw += 2 * P.nx;
+        if (P.wall_x) nw += 2 * (P.wall_y ? P.ny - 2 : P.ny);
+        for (int b = 0; b < nw; b += 64) c->work.push_back({k, 1, b, 0, std::min(64, nw - b), 0});
+    }
+    for (int k = 0; k < nc; ++k) {
+        const auto& P = c->P[k];
+        const int xlo = P.wall_x, xhi = P.wall_x ? P.nx - 1 : P.nx;
+        const int ylo = P.wall_y, yhi = P.wall_y ? P.ny - 1 : P.ny;
+        const int strips = (xhi - xlo + 61) / 62;
+        const int H = seg_rows > 0 ? seg_rows : auto_seg_rows(yhi - ylo, strips);
+        for (int y0 = ylo; y0 < yhi; y0 += H)
+            for (int s = 0; s < strips; ++s)
+                c->work.push_back({k, 0, xlo + 62 * s, y0, std::min(H, yhi - y0), 0});
+    }
+}
+
+lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* eos, const double* Pr,
+                       const double* gamma, const lbm_relax* relax, const lbm_boundary* bc,
+                       const lbm_options* opt, void* dev_ws, size_t ws_bytes, lbm_ctx** out)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    lbm_ctx* c = new lbm_ctx();
+    *out = c;
+    if (ncases < 1) return fail(c, LBM_EINVAL, "ncases must be >= 1");
+    if (!nx || !ny || !eos || !Pr || !gamma || !relax || !bc || !opt)
+        return fail(c, LBM_EINVAL, "null parameter block");
+    c->prec = opt[0].prec;
+    for (int k = 0; k < ncases; ++k) {
+        lbm_status st = validate(c, nx[k], ny[k], &eos[k], Pr[k], gamma[k], &relax[k], &bc[k], &opt[k]);
+        if (st != LBM_OK) return st;
+        if (opt[k].prec != c->prec) return fail(c, LBM_EINVAL, "all cases of a batch share one precision");
+    }
+    // device memory
+    size_t total = 0;
+    std::vector<Layout> L(ncases);
+    for (int k = 0; k < ncases; ++k) {
+        L[k] = layout_of(nx[k], ny[k], c->prec);
+        total += L[k].total;
+    }
+    char* base = nullptr;
+    if (dev_ws) {
+        if (ws_bytes < total) return fail(c, LBM_ENOMEM, "workspace smaller than lbm_workspace_bytes");
+        if (reinterpret_cast<uintptr_t>(dev_ws) % 256) return fail(c, LBM_EINVAL, "workspace must be 256-byte aligned");
+        base = static_cast<char*>(dev_ws);
+    } else {
+        void* p = nullptr;
+        if (hipMalloc(&p, total) != hipSuccess) return fail(c, LBM_ENOMEM, "hipMalloc of the lattice failed");
+        c->allocs.push_back(p);
+        base = static_cast<char*>(p);
+    }
+    if (opt[0].hip_stream) {
+        c->stream = static_cast<hipStream_t>(opt[0].hip_stream);
+    } else {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    HIP_TRY(c, hipMemsetAsync(base, 0, total, c->stream));
+    c->P.resize(ncases);
+    c->H.resize(ncases);
+    size_t off = 0;
+    for (int k = 0; k < ncases; ++k) {
+        build_case(c->P[k], nx[k], ny[k], eos[k], Pr[k], gamma[k], relax[k], bc[k], opt[k], L[k], base + off);
+        c->H[k].nx = nx[k];
+        c->H[k].ny = ny[k];
+        c->H[k].L = L[k];
+        c->H[k].base = base + off;
+        off += L[k].total;
+    }
+    build_work(c, opt[0].seg_rows);
+    void* p = nullptr;
+    HIP_TRY(c, hipMalloc(&p, sizeof(lbm::CaseParams) * ncases));
+    c->allocs.push_back(p);
+    c->d_P = static_cast<lbm::CaseParams*>(p);
+    HIP_TRY(c, hipMalloc(&p, sizeof(lbm::WorkItem) * c->work.size()));
+    c->allocs.push_back(p);
+    c->d_work = static_cast<lbm::WorkItem*>(p);
+    HIP_TRY(c, hipMalloc(&p, sizeof(double) * (kRedBlocks * 4 + 8)));
+    c->allocs.push_back(p);
+    c->d_red = static_cast<double*>(p);
+    HIP_TRY(c, hipMemcpyAsync(c->d_P, c->P.data(), sizeof(lbm::CaseParams) * ncases, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_work, c->work.data(), sizeof(lbm::WorkItem) * c->work.size(),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status check_ctx(lbm_ctx* c)
+{
+    if (!c) return LBM_EINVAL;
+    if (c->P.empty()) return fail(c, LBM_ESTATE, "context was not created successfully");
+    return LBM_OK;
+}
+
+lbm_status check_case(lbm_ctx* c, int k)
+{
+    lbm_status st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (k < 0 || k >= int(c->P.size())) return fail(c, LBM_EINVAL, "case index out of range");
+    return LBM_OK;
+}
+
+lbm_status read_flags(lbm_ctx* c, std::vector<int>& flags)
+{
+    flags.assign(c->P.size(), 0);
+    for (size_t k = 0; k < c->P.size(); ++k)
+        HIP_TRY(c, hipMemcpyAsync(&flags[k], c->P[k].flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t e0, hipEvent_t e1)
+{
+    for (size_t k = 0; k < c->H.size(); ++k)
+        if (!c->H[k].inited) return fail(c, LBM_ESTATE, "lbm_step before lbm_init of every case");
+    if (n < 0) return fail(c, LBM_EINVAL, "negative step count");
+    if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
+    for (long long s = 0; s < n; ++s) {
+        const int rc = lbm::launch_step(c->prec, c->d_P, c->d_work, int(c->work.size()), c->parity,
+                                        s == n - 1 ? 1 : 0, c->stream);
+        if (rc != 0) return hip_fail(c, hipError_t(rc), "step launch");
+        c->parity ^= 1;
+    }
+    if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
+    c->t += n;
+    std::vector<int> flags;
+    lbm_status st = read_flags(c, flags);
+    if (st != LBM_OK) return st;
+    for (size_t k = 0; k < flags.size(); ++k)
+        if (flags[k]) return fail(c, LBM_EDIVERGED, "case " + std::to_string(k) + " diverged");
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(int nx, int ny, int prec)
+{
+    if (nx < 1 || ny < 1 || prec < 0 || prec > 2) return 0;
+    return layout_of(nx, ny, prec).total;
+}
+
+lbm_status lbm_create(int nx, int ny, const lbm_eos* eos, double Pr, double gamma, const lbm_relax* relax,
+                      const lbm_boundary* bc, const lbm_options* opt, lbm_ctx** out)
+{
+    return create_impl(1, &nx, &ny, eos, &Pr, &gamma, relax, bc, opt, nullptr, 0, out);
+}
+
+lbm_status lbm_create_ex(int nx, int ny, const lbm_eos* eos, double Pr, double gamma, const lbm_relax* relax,
+                         const lbm_boundary* bc, const lbm_options* opt, void* dev_workspace, size_t bytes,
+                         lbm_ctx** out)
+{
+    if (!dev_workspace) {
+        if (out) *out = nullptr;
+        return LBM_EINVAL;
+    }
+    return create_impl(1, &nx, &ny, eos, &Pr, &gamma, relax, bc, opt, dev_workspace, bytes, out);
+}
+
+lbm_status lbm_batch_create(int ncases, const int* nx, const int* ny, const lbm_eos* eos, const double* Pr,
+                            const double* gamma, const lbm_relax* relax, const lbm_boundary* bc,
+                            const lbm_options* opt, lbm_ctx** out)
+{
+    if (!nx || !ny || !eos || !Pr || !gamma || !relax || !bc || !opt) {
+        if (out) *out = nullptr;
+        return LBM_EINVAL;
+    }
+    return create_impl(ncases, nx, ny, eos, Pr, gamma, relax, bc, opt, nullptr, 0, out);
+}
+
+int lbm_batch_size(const lbm_ctx* c) { return c ? int(c->P.size()) : 0; }
+
+long long lbm_work_items(const lbm_ctx* c) { return c ? (long long)c->work.size() : 0; }
+
+lbm_status lbm_case_init(lbm_ctx* c, int k, const double* rho, const double* ux, const double* uy, const double* T)
+{
+    lbm_status st = check_case(c, k);
+    if (st != LBM_OK) return st;
+    const auto& P = c->P[k];
+    const size_t nn = size_t(P.nx) * P.ny;
+    std::vector<double> h(4 * nn);
+    for (size_t i = 0; i < nn; ++i) {
+        h[i] = rho ? rho[i] : P.cd.rho0;
+        h[nn + i] = ux ? ux[i] : 0.0;
+        h[2 * nn + i] = uy ? uy[i] : 0.0;
+        h[3 * nn + i] = T ? T[i] : P.cd.T0;
+        if (!(h[i] > 0) || !(h[3 * nn + i] > 0) || !std::isfinite(h[i]) || !std::isfinite(h[nn + i]) ||
+            !std::isfinite(h[2 * nn + i]) || !std::isfinite(h[3 * nn + i]))
+            return fail(c, LBM_EINVAL, "initial fields must be finite with rho > 0 and T > 0");
+    }
+    void* d = nullptr;
+    HIP_TRY(c, hipMalloc(&d, h.size() * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(P.flag, 0, sizeof(int), c->stream);
+    int rc = 0;
+    if (e == hipSuccess)
+        rc = lbm::launch_init(c->prec, c->d_P, k, (long long)nn, static_cast<const double*>(d), c->parity, c->stream);
+    if (e == hipSuccess && rc == 0) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(c, e, "lbm_init");
+    if (rc != 0) return hip_fail(c, hipError_t(rc), "init launch");
+    c->H[k].inited = true;
+    if (c->P.size() == 1) c->t = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* T)
+{
+    return lbm_case_init(c, 0, rho, ux, uy, T);
+}
+
+lbm_status lbm_step(lbm_ctx* c, long long n)
+{
+    lbm_status st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    return run_steps(c, n, nullptr, nullptr);
+}
+
+lbm_status lbm_step_timed(lbm_ctx* c, long long n, double* ms)
+{
+    lbm_status st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    st = run_steps(c, n, e0, e1);
+    if (st == LBM_OK || st == LBM_EDIVERGED) {
+        float f = 0.f;
+        if (hipEventElapsedTime(&f, e0, e1) == hipSuccess && ms) *ms = f;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+lbm_status lbm_case_macros(lbm_ctx* c, int k, double* rho, double* ux, double* uy, double* T, double* p)
+{
+    lbm_status st = check_case(c, k);
+    if (st != LBM_OK) return st;
+    if (!c->H[k].inited) return fail(c, LBM_ESTATE, "case not initialised");
+    const auto& P = c->P[k];
+    const size_t nn = size_t(P.nx) * P.ny;
+    double* outs[5] = {rho, ux, uy, T, p};
+    for (int f = 0; f < 5; ++f)
+        if (outs[f])
+            HIP_TRY(c, hipMemcpyAsync(outs[f], P.macro + f * nn, nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_macros(lbm_ctx* c, double* rho, double* ux, double* uy, double* T, double* p)
+{
+    return lbm_case_macros(c, 0, rho, ux, uy, T, p);
+}
+
+lbm_status lbm_case_nusselt(lbm_ctx* c, int k, int side, double* nu)
+{
+    lbm_status st = check_case(c, k);
+    if (st != LBM_OK) return st;
+    if (!c->H[k].inited) return fail(c, LBM_ESTATE, "case not initialised");
+    const auto& P = c->P[k];
+    if (side < 0 || side > 3 || !nu) return fail(c, LBM_EINVAL, "bad side");
+    const int lo = side < 2 ? 0 : 2;
+    const bool walled = side < 2 ? P.wall_x : P.wall_y;
+    if (!walled || P.side_adiabatic[lo] || P.side_adiabatic[lo + 1] || P.cd.side_T[lo] == P.cd.side_T[lo + 1])
+        return fail(c, LBM_EINVAL, "Nusselt number needs Dirichlet walls with a temperature difference");
+    const int rc = lbm::launch_nusselt(c->d_P, k, side, c->d_red, c->stream);
+    if (rc != 0) return hip_fail(c, hipError_t(rc), "nusselt launch");
+    HIP_TRY(c, hipMemcpyAsync(nu, c->d_red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_nusselt(lbm_ctx* c, int side, double* nu) { return lbm_case_nusselt(c, 0, side, nu); }
+
+lbm_status lbm_case_totals(lbm_ctx* c, int k, double* mass, double* momx, double* momy, double* energy)
+{
+    lbm_status st = check_case(c, k);
+    if (st != LBM_OK) return st;
+    if (!c->H[k].inited) return fail(c, LBM_ESTATE, "case not initialised");
+    const int rc = lbm::launch_totals(c->d_P, k, c->d_red, kRedBlocks, c->d_red + kRedBlocks * 4, c->stream);
+    if (rc != 0) return hip_fail(c, hipError_t(rc), "totals launch");
+    double h[4];
+    HIP_TRY(c, hipMemcpyAsync(h, c->d_red + kRedBlocks * 4, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (mass) *mass = h[0];
+    if (momx) *momx = h[1];
+    if (momy) *momy = h[2];
+    if (energy) *energy = h[3];
+    return LBM_OK;
+}
+
+lbm_status lbm_totals(lbm_ctx* c, double* mass, double* momx, double* momy, double* energy)
+{
+    return lbm_case_totals(c, 0, mass, momx, momy, energy);
+}
+
+lbm_status lbm_batch_flags(lbm_ctx* c, int* diverged)
+{
+    lbm_status st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (!diverged) return fail(c, LBM_EINVAL, "null output");
+    std::vector<int> flags;
+    st = read_flags(c, flags);
+    if (st != LBM_OK) return st;
+    for (size_t k = 0; k < flags.size(); ++k) diverged[k] = flags[k] ? 1 : 0;
+    return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_ctx* c)
+{
+    if (!c) return 0;
+    size_t s = 16;
+    for (const auto& h : c->H) s += h.L.buf_bytes + h.L.macro_bytes;
+    return s;
+}
+
+lbm_status lbm_save(lbm_ctx* c, void* host, size_t bytes)
+{
+    lbm_status st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (!host || bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer smaller than lbm_state_bytes");
+    char* o = static_cast<char*>(host);
+    const long long hdr[2] = {c->t, (long long)c->P.size()};
+    std::memcpy(o, hdr, 16);
+    o += 16;
+    for (size_t k = 0; k < c->H.size(); ++k) {
+        const auto& h = c->H[k];
+        HIP_TRY(c, hipMemcpyAsync(o, h.base + c->parity * h.L.buf_bytes, h.L.buf_bytes, hipMemcpyDeviceToHost, c->stream));
+        o += h.L.buf_bytes;
+        HIP_TRY(c, hipMemcpyAsync(o, h.base + 2 * h.L.buf_bytes, h.L.macro_bytes, hipMemcpyDeviceToHost, c->stream));
+        o += h.L.macro_bytes;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_ctx* c, const void* host, size_t bytes)
+{
+    lbm_status st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (!host || bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer smaller than lbm_state_bytes");
+    const char* o = static_cast<const char*>(host);
+    long long hdr[2];
+    std::memcpy(hdr, o, 16);
+    if (hdr[1] != (long long)c->P.size()) return fail(c, LBM_EINVAL, "checkpoint has a different number of cases");
+    o += 16;
+    for (size_t k = 0; k < c->H.size(); ++k) {
+        auto& h = c->H[k];
+        HIP_TRY(c, hipMemcpyAsync(h.base + c->parity * h.L.buf_bytes, o, h.L.buf_bytes, hipMemcpyHostToDevice, c->stream));
+        o += h.L.buf_bytes;
+        HIP_TRY(c, hipMemcpyAsync(h.base + 2 * h.L.buf_bytes, o, h.L.macro_bytes, hipMemcpyHostToDevice, c->stream));
+        o += h.L.macro_bytes;
+        HIP_TRY(c, hipMemsetAsync(c->P[k].flag, 0, sizeof(int), c->stream));
+        h.inited = true;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->t = hdr[0];
+    return LBM_OK;
+}
+
+long long lbm_time(const lbm_ctx* c) { return c ? c->t : 0; }
+
+lbm_status lbm_copy_bandwidth(size_t bytes, int iters, void* hip_stream, double* gbps, double* ms_per_copy)
+{
+    if (bytes < 16 || bytes % 16 || iters < 1) return LBM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess) return LBM_ENOMEM;
+    if (hipMalloc(&b, bytes) != hipSuccess) {
+        (void)hipFree(a);
+        return LBM_ENOMEM;
+    }
+    lbm_status rc = LBM_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float ms = 0.f;
+    if (hipMemsetAsync(a, 0, bytes, st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        rc = LBM_EDEVICE;
+    } else {
+        lbm::launch_copy(a, b, (long long)bytes, st);   // warm-up
+        (void)hipEventRecord(e0, st);
+        for (int i = 0; i < iters; ++i) lbm::launch_copy(a, b, (long long)bytes, st);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = LBM_EDEVICE;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    if (rc == LBM_OK) {
+        const double per = ms / iters;
+        if (ms_per_copy) *ms_per_copy = per;
+        if (gbps) *gbps = 2.0 * double(bytes) / (per * 1e-3) / 1e9;
+    }
+    return rc;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void lbm_destroy(lbm_ctx* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,716 @@
+// Kernels of the coupled D2Q9 MRT step (Huang, Wu & Adams, arXiv:1809.08683)
+// for gfx950.
+//
+// Storage: two ping-pong buffers of 18 SoA planes (f_0..f_8, g_0..g_8), each
+// plane (ny + 2) rows of `pitch` elements; node (x, y) sits at row y + 1,
+// column x + 1.  The extra frame holds ghost cells on walled sides: a wall
+// node writes every post-collision DF that would leave the domain into the
+// ghost cell it would reach, in the plane of the opposite direction, so the
+// next step's pull reads the bounce-back temporaries of eqs. BB.f and BB.g
+// without any special case.  Periodic sides wrap in the index arithmetic.
+//
+// One step is one launch.  Each wavefront takes one work item:
+//   - interior item: 64 lanes span 62 output columns plus one halo column
+//     on each side and march up a segment of rows with a rolling window of
+//     three rows of (rho, p), so that grad(rho) and grad(p) of the correction
+//     terms use same-time-level neighbours; x-neighbours come from lane
+//     shuffles, y-neighbours from the window;
+//   - wall item: 64 wall nodes; each lane completes its node's macros
+//     (Sec. 3.1), extrapolates the tilde non-equilibrium moments from x_f,
+//     x_ff (eqs. neq.redefinition, neq.extrapolation), inverts them with the
+//     closed forms of App. B, collides and writes its ghost cells.
+#include <algorithm>
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+constexpr int WAVE = 64;
+constexpr int STRIP = WAVE - 2;
+constexpr int WAVES_PER_BLOCK = 4;
+
+#define EXq(q) ((q) == 1 || (q) == 5 || (q) == 8 ? 1 : ((q) == 3 || (q) == 6 || (q) == 7 ? -1 : 0))
+#define EYq(q) ((q) == 2 || (q) == 5 || (q) == 6 ? 1 : ((q) == 4 || (q) == 7 || (q) == 8 ? -1 : 0))
+#define OPPq(q) ((q) == 0 ? 0 : ((q) <= 4 ? (((q) + 1) % 4) + 1 : (((q) - 5 + 2) % 4) + 5))
+
+__device__ __forceinline__ int wrap_axis(int v, int n, int walled)
+{
+    if (walled) return v;
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+__device__ __forceinline__ long long node_index(const CaseParams& P, int x, int y)
+{
+    return (long long)(wrap_axis(y, P.ny, P.wall_y) + 1) * P.pitch + (wrap_axis(x, P.nx, P.wall_x) + 1);
+}
+
+// side indices of a node: x-side (0/1) or -1, y-side (2/3) or -1
+__device__ __forceinline__ int side_x(const CaseParams& P, int x)
+{
+    return P.wall_x ? (x == 0 ? 0 : (x == P.nx - 1 ? 1 : -1)) : -1;
+}
+__device__ __forceinline__ int side_y(const CaseParams& P, int y)
+{
+    return P.wall_y ? (y == 0 ? 2 : (y == P.ny - 1 ? 3 : -1)) : -1;
+}
+
+// Macros of a node from its pulled moments: off-wall nodes from the DFs,
+// wall nodes from the bounce-back completed sums and the prescribed values.
+// The x-wall sets the velocity of a corner and its temperature when it is
+// Dirichlet; otherwise a Dirichlet y-wall sets the temperature.
+template <typename C>
+__device__ __forceinline__ C node_state(const CaseParams& P, const Coef<C>& K, int sx, int sy,
+                                        const C m[9], C n0, NodeState<C>& s)
+{
+    if (sx < 0 && sy < 0) return state_from_moments<C>(K, P.eos, P.per_mass, m, n0, s);
+    const int sv = sx >= 0 ? sx : sy;
+    int adiabatic = 1;
+    double Tw = 0.0;
+    if (sx >= 0 && !P.side_adiabatic[sx]) { adiabatic = 0; Tw = K.side_T[sx]; }
+    else if (sy >= 0 && !P.side_adiabatic[sy]) { adiabatic = 0; Tw = K.side_T[sy]; }
+    return state_wall<C>(K, P.eos, P.per_mass, m[0], n0, K.side_ux[sv], K.side_uy[sv],
+                         adiabatic, Tw, s);
+}
+
+// Pull the 18 DFs of node (x, y) (generic indexing) and take their moments.
+template <typename S, typename C>
+__device__ __forceinline__ void pull_node(const CaseParams& P, const S* src, int x, int y, C m[9], C n[9])
+{
+    C f[9], g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const long long idx = node_index(P, x - EXq(q), y - EYq(q));
+        f[q] = Store<S>::load(src + q * P.plane + idx);
+        g[q] = Store<S>::load(src + (9 + q) * P.plane + idx);
+    }
+    to_moments<C>(f, m);
+    to_moments<C>(g, n);
+}
+
+template <typename S>
+__device__ __forceinline__ void store_node(const CaseParams& P, S* dst, long long idx,
+                                           const typename Store<S>::C fb[9], const typename Store<S>::C gb[9])
+{
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        Store<S>::store(dst + q * P.plane + idx, fb[q]);
+        Store<S>::store(dst + (9 + q) * P.plane + idx, gb[q]);
+    }
+}
+
+// Write the post-collision DFs of a wall node that leave the domain into the
+// ghost cells they reach, in the plane of the opposite direction.
+template <typename S>
+__device__ __forceinline__ void store_ghosts(const CaseParams& P, S* dst, int x, int y,
+                                             const typename Store<S>::C fb[9], const typename Store<S>::C gb[9])
+{
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+        const int tx = x + EXq(q), ty = y + EYq(q);
+        const bool out = (P.wall_x && (tx < 0 || tx >= P.nx)) || (P.wall_y && (ty < 0 || ty >= P.ny));
+        if (out) {
+            const long long idx = node_index(P, tx, ty);
+            Store<S>::store(dst + OPPq(q) * P.plane + idx, fb[q]);
+            Store<S>::store(dst + (9 + OPPq(q)) * P.plane + idx, gb[q]);
+        }
+    }
+}
+
+template <typename C>
+__device__ __forceinline__ void export_node(const CaseParams& P, int x, int y, const NodeState<C>& s)
+{
+    const long long nn = (long long)P.nx * P.ny;
+    const long long i = (long long)y * P.nx + x;
+    P.macro[i] = coef<C>(P).rho0_d + double(s.drho);
+    P.macro[nn + i] = double(s.ux);
+    P.macro[2 * nn + i] = double(s.uy);
+    P.macro[3 * nn + i] = s.Td;
+    P.macro[4 * nn + i] = coef<C>(P).p0_d + double(s.dp);
+    const bool ok = s.rho > C(0) && s.Td > 0.0 && s.rho < C(1e30) && s.Td < 1e30 &&
+                    s.ux == s.ux && s.uy == s.uy && s.p == s.p;
+    if (!ok) atomicOr(P.flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// collision of a node given its pulled moments
+// ---------------------------------------------------------------------------
+template <typename C>
+__device__ __forceinline__ void collide_interior(const CaseParams& P, const Coef<C>& K, const NodeState<C>& s,
+                                                 C inv_rho, const C m[9], const C n[9],
+                                                 C gr_x, C gr_y, C gp_x, C gp_y, C fb[9], C gb[9])
+{
+    Rates<C> r;
+    local_rates<C>(K, P.visc_law, s.rho, inv_rho, s.T, r);
+    C meq[9], Fm[9], neq[9], Qm[9], N[9], Nt[9], Hm[9], Ht[9], mb[9], nb[9];
+    meq_f<C>(s, meq);
+    force_moments<C>(s, Fm);
+    neq_g<C>(K, s, neq);
+    source_moments<C>(s, Qm);
+    nonequilibrium<C>(s, r, m, n, meq, Fm, neq, Qm, N, Nt, Hm, Ht);
+    post_collision<C>(s, r, P.cubic, meq, Fm, N, Nt, neq, Qm, Hm, Ht, gr_x, gr_y, gp_x, gp_y, mb, nb);
+    from_moments<C>(mb, fb);
+    from_moments<C>(nb, gb);
+}
+
+// ---------------------------------------------------------------------------
+// interior item: march up a strip segment
+// ---------------------------------------------------------------------------
+template <typename C>
+__device__ __forceinline__ C from_left(C v) { return __shfl_up(v, 1, WAVE); }
+template <typename C>
+__device__ __forceinline__ C from_right(C v) { return __shfl_down(v, 1, WAVE); }
+
+template <typename S>
+__device__ void interior_item(const CaseParams& P, const WorkItem& w, const S* __restrict__ src,
+                              S* __restrict__ dst, int export_macros)
+{
+    using C = typename Store<S>::C;
+    const Coef<C>& K = coef<C>(P);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int xhi = P.wall_x ? P.nx - 1 : P.nx;
+    const int x = w.x0 - 1 + lane;
+    const bool out_lane = lane >= 1 && lane <= STRIP && x < xhi;
+    const int xc = min(x, xhi);                    // lanes past the halo mirror a valid node
+    const int sx = side_x(P, xc);
+
+    C m_c[9], n_c[9], m_n[9], n_n[9];
+    NodeState<C> s_c, s_n;
+    C inv_c = C(0), inv_n = C(0);
+    C rho_m = C(0), p_m = C(0);
+
+    auto pull_row = [&](int yy, C mm[9], C nn[9]) {
+        const long long rows[3] = {
+            (long long)(wrap_axis(yy - 1, P.ny, P.wall_y) + 1) * P.pitch,   // source y - 1 (e_y = +1)
+            (long long)(wrap_axis(yy, P.ny, P.wall_y) + 1) * P.pitch,       // e_y = 0
+            (long long)(wrap_axis(yy + 1, P.ny, P.wall_y) + 1) * P.pitch};  // e_y = -1
+        C f[9], g[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const long long idx = rows[1 - EYq(q)] + (wrap_axis(xc - EXq(q), P.nx, P.wall_x) + 1);
+            f[q] = Store<S>::load(src + q * P.plane + idx);
+            g[q] = Store<S>::load(src + (9 + q) * P.plane + idx);
+        }
+        to_moments<C>(f, mm);
+        to_moments<C>(g, nn);
+    };
+
+    const int y0 = w.y0;
+    // halo row below the segment: only rho and p are kept
+    {
+        C mm[9], nn[9];
+        NodeState<C> st;
+        const int yy = y0 - 1;
+        pull_row(yy, mm, nn);
+        const int yw = wrap_axis(yy, P.ny, P.wall_y);
+        node_state<C>(P, K, sx, side_y(P, yw), mm, nn[0], st);
+        rho_m = st.drho;
+        p_m = st.dp;
+    }
+    pull_row(y0, m_c, n_c);
+    inv_c = node_state<C>(P, K, sx, side_y(P, y0), m_c, n_c[0], s_c);
+
+    for (int i = 0; i < w.len; ++i) {
+        const int y = y0 + i;
+        const int yn = wrap_axis(y + 1, P.ny, P.wall_y);
+        pull_row(y + 1, m_n, n_n);
+        inv_n = node_state<C>(P, K, sx, side_y(P, yn), m_n, n_n[0], s_n);
+
+        // isotropic gradients d_a phi = 3 sum_q w_q e_qa phi(x + e_q), taken on
+        // the deviations rho - rho0 and p - p0
+        const C rW = from_left(s_c.drho), rE = from_right(s_c.drho);
+        const C rSW = from_left(rho_m), rSE = from_right(rho_m);
+        const C rNW = from_left(s_n.drho), rNE = from_right(s_n.drho);
+        const C pW = from_left(s_c.dp), pE = from_right(s_c.dp);
+        const C pSW = from_left(p_m), pSE = from_right(p_m);
+        const C pNW = from_left(s_n.dp), pNE = from_right(s_n.dp);
+        const C gr_x = (rE - rW) * C(1.0 / 3.0) + (rNE + rSE - rNW - rSW) * C(1.0 / 12.0);
+        const C gr_y = (s_n.drho - rho_m) * C(1.0 / 3.0) + (rNE + rNW - rSE - rSW) * C(1.0 / 12.0);
+        const C gp_x = (pE - pW) * C(1.0 / 3.0) + (pNE + pSE - pNW - pSW) * C(1.0 / 12.0);
+        const C gp_y = (s_n.dp - p_m) * C(1.0 / 3.0) + (pNE + pNW - pSE - pSW) * C(1.0 / 12.0);
+
+        if (out_lane) {
+            C fb[9], gb[9];
+            collide_interior<C>(P, K, s_c, inv_c, m_c, n_c, gr_x, gr_y, gp_x, gp_y, fb, gb);
+            const long long idx = (long long)(y + 1) * P.pitch + (x + 1);
+            store_node<S>(P, dst, idx, fb, gb);
+            if (export_macros) export_node<C>(P, x, y, s_c);
+        }
+        rho_m = s_c.drho;
+        p_m = s_c.dp;
+        s_c = s_n;
+        inv_c = inv_n;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            m_c[q] = m_n[q];
+            n_c[q] = n_n[q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// wall item
+// ---------------------------------------------------------------------------
+// Wall nodes of a case, enumerated as: bottom row, top row (walled y), then
+// left and right columns without the corners (walled x).
+__device__ __forceinline__ int wall_node_count(const CaseParams& P)
+{
+    int n = 0;
+    if (P.wall_y) n += 2 * P.nx;
+    if (P.wall_x) n += 2 * (P.wall_y ? P.ny - 2 : P.ny);
+    return n;
+}
+
+__device__ __forceinline__ void wall_node_xy(const CaseParams& P, int i, int& x, int& y)
+{
+    if (P.wall_y) {
+        if (i < P.nx) { x = i; y = 0; return; }
+        i -= P.nx;
+        if (i < P.nx) { x = i; y = P.ny - 1; return; }
+        i -= P.nx;
+    }
+    const int ylo = P.wall_y ? 1 : 0, len = P.wall_y ? P.ny - 2 : P.ny;
+    if (i < len) { x = 0; y = ylo + i; return; }
+    i -= len;
+    x = P.nx - 1;
+    y = ylo + i;
+}
+
+template <typename S>
+__device__ __forceinline__ typename Store<S>::C node_rho_p(const CaseParams& P, const S* src, int x, int y,
+                                                          typename Store<S>::C& p)
+{
+    using C = typename Store<S>::C;
+    C m[9], n[9];
+    NodeState<C> s;
+    pull_node<S, C>(P, src, x, y, m, n);
+    const int xw = wrap_axis(x, P.nx, P.wall_x), yw = wrap_axis(y, P.ny, P.wall_y);
+    node_state<C>(P, coef<C>(P), side_x(P, xw), side_y(P, yw), m, n[0], s);
+    p = s.dp;
+    return s.drho;
+}
+
+// derivative of rho and p (as deviations) along one axis at a wall node (second-order
+// one-sided towards the inside along a walled axis it lies on, two-point
+// central otherwise)
+template <typename S>
+__device__ __forceinline__ void wall_axis_gradient(const CaseParams& P, const S* src, int x, int y, int ax,
+                                                   typename Store<S>::C rho0, typename Store<S>::C p0,
+                                                   typename Store<S>::C& gr, typename Store<S>::C& gp)
+{
+    using C = typename Store<S>::C;
+    const int dx = ax == 0 ? 1 : 0, dy = ax == 0 ? 0 : 1;
+    const int s = ax == 0 ? side_x(P, x) : side_y(P, y);
+    C p1, p2;
+    if (s == 0 || s == 2) {
+        const C r1 = node_rho_p<S>(P, src, x + dx, y + dy, p1);
+        const C r2 = node_rho_p<S>(P, src, x + 2 * dx, y + 2 * dy, p2);
+        gr = (C(-3) * rho0 + C(4) * r1 - r2) * C(0.5);
+        gp = (C(-3) * p0 + C(4) * p1 - p2) * C(0.5);
+    } else if (s == 1 || s == 3) {
+        const C r1 = node_rho_p<S>(P, src, x - dx, y - dy, p1);
+        const C r2 = node_rho_p<S>(P, src, x - 2 * dx, y - 2 * dy, p2);
+        gr = (C(3) * rho0 - C(4) * r1 + r2) * C(0.5);
+        gp = (C(3) * p0 - C(4) * p1 + p2) * C(0.5);
+    } else {
+        const C r1 = node_rho_p<S>(P, src, x + dx, y + dy, p1);
+        const C r2 = node_rho_p<S>(P, src, x - dx, y - dy, p2);
+        gr = (r1 - r2) * C(0.5);
+        gp = (p1 - p2) * C(0.5);
+    }
+}
+
+// Tilde non-equilibrium moments of an off-wall node (eq. neq.redefinition):
+//   Zm = (I - S/2) m^neq,  Zn = (I - L/2) n^neq + (Y/2) Zm
+template <typename S>
+__device__ __forceinline__ void tilde_at(const CaseParams& P, const S* src, int x, int y,
+                                         typename Store<S>::C Zm[9], typename Store<S>::C Zn[9])
+{
+    using C = typename Store<S>::C;
+    const Coef<C>& K = coef<C>(P);
+    C m[9], n[9];
+    NodeState<C> s;
+    pull_node<S, C>(P, src, x, y, m, n);
+    const C inv_rho = node_state<C>(P, K, -1, -1, m, n[0], s);
+    Rates<C> r;
+    local_rates<C>(K, P.visc_law, s.rho, inv_rho, s.T, r);
+    C meq[9], Fm[9], neq[9], Qm[9], N[9], Hm[9];
+    meq_f<C>(s, meq);
+    force_moments<C>(s, Fm);
+    neq_g<C>(K, s, neq);
+    source_moments<C>(s, Qm);
+    nonequilibrium<C>(s, r, m, n, meq, Fm, neq, Qm, N, Zm, Hm, Zn);
+    const C y3 = s.ux * (C(1.0 / 3.0) * Zm[1] + Zm[7]) + C(2) * s.uy * Zm[8];
+    const C y5 = s.uy * (C(1.0 / 3.0) * Zm[1] - Zm[7]) + C(2) * s.ux * Zm[8];
+    Zn[3] += C(0.5) * y3;
+    Zn[4] -= C(0.5) * y3;
+    Zn[5] += C(0.5) * y5;
+    Zn[6] -= C(0.5) * y5;
+}
+
+template <typename S>
+__device__ void wall_item(const CaseParams& P, const WorkItem& w, const S* __restrict__ src,
+                          S* __restrict__ dst, int export_macros)
+{
+    using C = typename Store<S>::C;
+    const Coef<C>& K = coef<C>(P);
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (lane >= w.len) return;
+    int xb, yb;
+    wall_node_xy(P, w.x0 + lane, xb, yb);
+    const int sx = side_x(P, xb), sy = side_y(P, yb);
+
+    // macros of the wall node from the bounce-back completed DFs (Sec. 3.1)
+    C m[9], n[9];
+    NodeState<C> s;
+    pull_node<S, C>(P, src, xb, yb, m, n);
+    const C inv_rho = node_state<C>(P, K, sx, sy, m, n[0], s);
+
+    // extrapolated tilde non-equilibrium moments (eq. neq.extrapolation)
+    const int ndx = sx == 0 ? 1 : (sx == 1 ? -1 : 0);
+    const int ndy = sy == 2 ? 1 : (sy == 3 ? -1 : 0);
+    C Zm[9], Zn[9];
+    tilde_at<S>(P, src, xb + ndx, yb + ndy, Zm, Zn);
+    if (P.extrap_order == 2) {
+        C Zm2[9], Zn2[9];
+        tilde_at<S>(P, src, xb + 2 * ndx, yb + 2 * ndy, Zm2, Zn2);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            Zm[q] = C(2) * Zm[q] - Zm2[q];
+            Zn[q] = C(2) * Zn[q] - Zn2[q];
+        }
+    }
+    Zm[0] = C(0);
+    Zm[3] = C(0);
+    Zm[5] = C(0);
+    Zn[0] = C(0);
+
+    // invert with the wall node's own S, L, Y (App. B)
+    Rates<C> r;
+    local_rates<C>(K, P.visc_law, s.rho, inv_rho, s.T, r);
+    C N[9], Ht[9], Hm[9];
+    untilde_f<C>(s, r, Zm, N);
+    {
+        const C y3 = s.ux * (C(1.0 / 3.0) * Zm[1] + Zm[7]) + C(2) * s.uy * Zm[8];
+        const C y5 = s.uy * (C(1.0 / 3.0) * Zm[1] - Zm[7]) + C(2) * s.ux * Zm[8];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Ht[q] = Zn[q];
+        Ht[3] -= C(0.5) * y3;
+        Ht[4] += C(0.5) * y3;
+        Ht[5] -= C(0.5) * y5;
+        Ht[6] += C(0.5) * y5;
+    }
+    untilde_g<C>(r, Ht, Hm);
+
+    // gradients at the wall node
+    C gr_x, gr_y, gp_x, gp_y;
+    wall_axis_gradient<S>(P, src, xb, yb, 0, s.drho, s.dp, gr_x, gp_x);
+    wall_axis_gradient<S>(P, src, xb, yb, 1, s.drho, s.dp, gr_y, gp_y);
+
+    C meq[9], Fm[9], neq[9], Qm[9], mb[9], nb[9], fb[9], gb[9];
+    meq_f<C>(s, meq);
+    force_moments<C>(s, Fm);
+    neq_g<C>(K, s, neq);
+    source_moments<C>(s, Qm);
+    post_collision<C>(s, r, P.cubic, meq, Fm, N, Zm, neq, Qm, Hm, Ht, gr_x, gr_y, gp_x, gp_y, mb, nb);
+    from_moments<C>(mb, fb);
+    from_moments<C>(nb, gb);
+    const long long idx = (long long)(yb + 1) * P.pitch + (xb + 1);
+    store_node<S>(P, dst, idx, fb, gb);
+    store_ghosts<S>(P, dst, xb, yb, fb, gb);
+    if (export_macros) export_node<C>(P, xb, yb, s);
+}
+
+// ---------------------------------------------------------------------------
+// step kernel
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(WAVE * WAVES_PER_BLOCK) void step_kernel(
+    const CaseParams* __restrict__ cases, const WorkItem* __restrict__ work, int nwork, int parity,
+    int export_macros)
+{
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6));
+    if (wid >= nwork) return;
+    const WorkItem w = work[wid];
+    const CaseParams& P = cases[w.case_id];
+    const S* src = static_cast<const S*>(P.buf[parity]);
+    S* dst = static_cast<S*>(P.buf[parity ^ 1]);
+    if (w.kind == 0)
+        interior_item<S>(P, w, src, dst, export_macros);
+    else
+        wall_item<S>(P, w, src, dst, export_macros);
+}
+
+// ---------------------------------------------------------------------------
+// initial state (t = 0): m = m^eq - F_m/2, n = n^eq - Q_m/2 at every node,
+// collided with gradients of the initial fields, written post-collision into
+// the current source buffer (with ghost cells) and exported
+// ---------------------------------------------------------------------------
+template <typename C>
+__device__ __forceinline__ void init_state(const CaseParams& P, const Coef<C>& K, const double* fld, int x, int y,
+                                           NodeState<C>& s, C& inv_rho)
+{
+    const long long nn = (long long)P.nx * P.ny;
+    const long long i = (long long)y * P.nx + x;
+    inv_rho = state_prescribed<C>(K, P.eos, P.per_mass, fld[i], fld[nn + i], fld[2 * nn + i], fld[3 * nn + i], s);
+}
+
+template <typename C>
+__device__ __forceinline__ void init_rho_p(const CaseParams& P, const Coef<C>& K, const double* fld, int x, int y,
+                                           C& rho, C& p)
+{
+    const int xw = wrap_axis(x, P.nx, P.wall_x), yw = wrap_axis(y, P.ny, P.wall_y);
+    const long long nn = (long long)P.nx * P.ny;
+    const long long i = (long long)yw * P.nx + xw;
+    rho = C(fld[i] - K.rho0_d);
+    p = C(eos_pressure_d<C>(K, P.eos, fld[i], fld[3 * nn + i]) - K.p0_d);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void init_kernel(const CaseParams* __restrict__ cases, int case_id,
+                                                   const double* __restrict__ fld, int parity)
+{
+    using C = typename Store<S>::C;
+    const CaseParams& P = cases[case_id];
+    const Coef<C>& K = coef<C>(P);
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long long)P.nx * P.ny) return;
+    const int x = int(gid % P.nx), y = int(gid / P.nx);
+    NodeState<C> s;
+    C inv_rho;
+    init_state<C>(P, K, fld, x, y, s, inv_rho);
+    const int sx = side_x(P, x), sy = side_y(P, y);
+    C gr[2], gp[2];
+    if (sx < 0 && sy < 0) {
+        C sr[2] = {C(0), C(0)}, spp[2] = {C(0), C(0)};
+#pragma unroll
+        for (int q = 1; q < 9; ++q) {
+            C r, p;
+            init_rho_p<C>(P, K, fld, x + EXq(q), y + EYq(q), r, p);
+            const C wq = (q <= 4) ? C(1.0 / 3.0) : C(1.0 / 12.0);   // 3 w_q
+            sr[0] += wq * C(EXq(q)) * r;
+            sr[1] += wq * C(EYq(q)) * r;
+            spp[0] += wq * C(EXq(q)) * p;
+            spp[1] += wq * C(EYq(q)) * p;
+        }
+        gr[0] = sr[0]; gr[1] = sr[1]; gp[0] = spp[0]; gp[1] = spp[1];
+    } else {
+#pragma unroll
+        for (int ax = 0; ax < 2; ++ax) {
+            const int dx = ax == 0 ? 1 : 0, dy = ax == 0 ? 0 : 1;
+            const int sd = ax == 0 ? sx : sy;
+            C r1, p1, r2, p2;
+            if (sd == 0 || sd == 2) {
+                init_rho_p<C>(P, K, fld, x + dx, y + dy, r1, p1);
+                init_rho_p<C>(P, K, fld, x + 2 * dx, y + 2 * dy, r2, p2);
+                gr[ax] = (C(-3) * s.drho + C(4) * r1 - r2) * C(0.5);
+                gp[ax] = (C(-3) * s.dp + C(4) * p1 - p2) * C(0.5);
+            } else if (sd == 1 || sd == 3) {
+                init_rho_p<C>(P, K, fld, x - dx, y - dy, r1, p1);
+                init_rho_p<C>(P, K, fld, x - 2 * dx, y - 2 * dy, r2, p2);
+                gr[ax] = (C(3) * s.drho - C(4) * r1 + r2) * C(0.5);
+                gp[ax] = (C(3) * s.dp - C(4) * p1 + p2) * C(0.5);
+            } else {
+                init_rho_p<C>(P, K, fld, x + dx, y + dy, r1, p1);
+                init_rho_p<C>(P, K, fld, x - dx, y - dy, r2, p2);
+                gr[ax] = (r1 - r2) * C(0.5);
+                gp[ax] = (p1 - p2) * C(0.5);
+            }
+        }
+    }
+    Rates<C> r;
+    local_rates<C>(K, P.visc_law, s.rho, inv_rho, s.T, r);
+    C meq[9], Fm[9], neq[9], Qm[9], Z[9], mb[9], nb[9], fb[9], gb[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Z[q] = C(0);
+    meq_f<C>(s, meq);
+    force_moments<C>(s, Fm);
+    neq_g<C>(K, s, neq);
+    source_moments<C>(s, Qm);
+    post_collision<C>(s, r, P.cubic, meq, Fm, Z, Z, neq, Qm, Z, Z, gr[0], gr[1], gp[0], gp[1], mb, nb);
+    from_moments<C>(mb, fb);
+    from_moments<C>(nb, gb);
+    S* dst = static_cast<S*>(P.buf[parity]);
+    const long long idx = (long long)(y + 1) * P.pitch + (x + 1);
+    store_node<S>(P, dst, idx, fb, gb);
+    if (sx >= 0 || sy >= 0) store_ghosts<S>(P, dst, x, y, fb, gb);
+    export_node<C>(P, x, y, s);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions (deterministic: fixed per-thread order, fixed tree)
+// ---------------------------------------------------------------------------
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Partial sums of rho, rho ux, rho uy, rho E over rows of the exported
+// macros; out[block * 4 + k].
+__global__ __launch_bounds__(RED_THREADS) void totals_partial(const CaseParams* __restrict__ cases, int case_id,
+                                                              double* __restrict__ out)
+{
+    __shared__ double sh[RED_THREADS];
+    const CaseParams& P = cases[case_id];
+    const long long nn = (long long)P.nx * P.ny;
+    const long long per = (nn + gridDim.x - 1) / gridDim.x;
+    const long long lo = blockIdx.x * per, hi = min(nn, lo + per);
+    double a[4] = {0, 0, 0, 0};
+    for (long long i = lo + threadIdx.x; i < hi; i += RED_THREADS) {
+        const double rho = P.macro[i], ux = P.macro[nn + i], uy = P.macro[2 * nn + i], T = P.macro[3 * nn + i];
+        a[0] += rho;
+        a[1] += rho * ux;
+        a[2] += rho * uy;
+        a[3] += rho * (P.cd.cv_d * T + 0.5 * (ux * ux + uy * uy));
+    }
+    for (int k = 0; k < 4; ++k) {
+        const double s = block_sum(a[k], sh);
+        if (threadIdx.x == 0) out[blockIdx.x * 4 + k] = s;
+    }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void sum_partials(const double* __restrict__ in, int nblocks,
+                                                            double* __restrict__ out)
+{
+    __shared__ double sh[RED_THREADS];
+    for (int k = 0; k < 4; ++k) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) a += in[b * 4 + k];
+        const double s = block_sum(a, sh);
+        if (threadIdx.x == 0) out[k] = s;
+    }
+}
+
+// Mean Nusselt number through a Dirichlet side: trapezoid rule along the
+// side of J_n = -lambda(T) dT/dn with a second-order one-sided dT/dn,
+// divided by lambda0 (T_lo - T_hi) of that axis.  mu(T)/mu0 is evaluated in
+// FP64; lambda = C_p mu / Pr cancels C_p / Pr against lambda0.
+__global__ __launch_bounds__(RED_THREADS) void nusselt_kernel(const CaseParams* __restrict__ cases, int case_id,
+                                                              int side, double* __restrict__ out)
+{
+    __shared__ double sh[RED_THREADS];
+    const CaseParams& P = cases[case_id];
+    const int nx = P.nx, ny = P.ny;
+    const long long nn = (long long)nx * ny;
+    const double* T = P.macro + 3 * nn;
+    const int len = side < 2 ? ny : nx;
+    const int lo = side < 2 ? 0 : 2;
+    const double dT = P.cd.side_T[lo] - P.cd.side_T[lo + 1];
+    const double S = P.cd.suth_S, T0 = P.cd.T0;
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < len; j += RED_THREADS) {
+        double t0, t1, t2, d;
+        if (side < 2) {
+            const int x0 = side == 0 ? 0 : nx - 1;
+            d = side == 0 ? 1.0 : -1.0;
+            const int s1 = side == 0 ? 1 : -1;
+            t0 = T[(long long)j * nx + x0];
+            t1 = T[(long long)j * nx + x0 + s1];
+            t2 = T[(long long)j * nx + x0 + 2 * s1];
+        } else {
+            const int y0 = side == 2 ? 0 : ny - 1;
+            d = side == 2 ? 1.0 : -1.0;
+            const int s1 = side == 2 ? 1 : -1;
+            t0 = T[(long long)y0 * nx + j];
+            t1 = T[(long long)(y0 + s1) * nx + j];
+            t2 = T[(long long)(y0 + 2 * s1) * nx + j];
+        }
+        const double dTdn = d * (-3.0 * t0 + 4.0 * t1 - t2) * 0.5;
+        double mu_rel;
+        const double th = t0 / T0;
+        if (P.visc_law == VISC_CONST) mu_rel = 1.0;
+        else if (P.visc_law == VISC_LINEAR) mu_rel = th;
+        else mu_rel = th * sqrt(th) * (1.0 + S) / (th + S);
+        const double wgt = (j == 0 || j == len - 1) ? 0.5 : 1.0;
+        acc += wgt * (-mu_rel * dTdn);
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[0] = s / dT;
+}
+
+// ---------------------------------------------------------------------------
+// plain copy (measured-bandwidth probe and byte-counter calibration)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                   long long n)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+int launch_copy(const void* src, void* dst, long long bytes, hipStream_t stream)
+{
+    const long long n = bytes / 16;
+    const unsigned blocks = unsigned(std::min<long long>((n + 255) / 256, 256 * 64));
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, stream, static_cast<const float4*>(src),
+                       static_cast<float4*>(dst), n);
+    return int(hipGetLastError());
+}
+
+int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
+                int export_macros, hipStream_t stream)
+{
+    const int blocks = (nwork + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    if (blocks == 0) return 0;
+    const dim3 grid(blocks), block(WAVE * WAVES_PER_BLOCK);
+    switch (prec) {
+    case PREC_F64:
+        hipLaunchKernelGGL(step_kernel<double>, grid, block, 0, stream, d_cases, d_work, nwork, parity, export_macros);
+        break;
+    case PREC_F32:
+        hipLaunchKernelGGL(step_kernel<float>, grid, block, 0, stream, d_cases, d_work, nwork, parity, export_macros);
+        break;
+    default:
+        hipLaunchKernelGGL(step_kernel<__half>, grid, block, 0, stream, d_cases, d_work, nwork, parity, export_macros);
+        break;
+    }
+    return int(hipGetLastError());
+}
+
+int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
+                int parity, hipStream_t stream)
+{
+    const dim3 grid(unsigned((nodes + 255) / 256)), block(256);
+    switch (prec) {
+    case PREC_F64:
+        hipLaunchKernelGGL(init_kernel<double>, grid, block, 0, stream, d_cases, case_id, d_fields, parity);
+        break;
+    case PREC_F32:
+        hipLaunchKernelGGL(init_kernel<float>, grid, block, 0, stream, d_cases, case_id, d_fields, parity);
+        break;
+    default:
+        hipLaunchKernelGGL(init_kernel<__half>, grid, block, 0, stream, d_cases, case_id, d_fields, parity);
+        break;
+    }
+    return int(hipGetLastError());
+}
+
+int launch_totals(const CaseParams* d_cases, int case_id, double* d_partial, int nblocks, double* d_out,
+                  hipStream_t stream)
+{
+    hipLaunchKernelGGL(totals_partial, dim3(nblocks), dim3(RED_THREADS), 0, stream, d_cases, case_id, d_partial);
+    hipLaunchKernelGGL(sum_partials, dim3(1), dim3(RED_THREADS), 0, stream, d_partial, nblocks, d_out);
+    return int(hipGetLastError());
+}
+
+int launch_nusselt(const CaseParams* d_cases, int case_id, int side, double* d_out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(nusselt_kernel, dim3(1), dim3(RED_THREADS), 0, stream, d_cases, case_id, side, d_out);
+    return int(hipGetLastError());
+}
+
+}  // namespace lbm

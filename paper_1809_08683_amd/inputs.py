@@ -106,34 +106,43 @@ def bulk_ratio_for_ra(Ra: float) -> float:
     return 4.0
 
 
-def cavity(N=512, Ra=1e6, eps=0.6, Pr=0.71, Ma=0.05, bulk_ratio=None, noise_seed=None,
+def cavity(N=512, Ra=1e6, eps=0.6, Pr=0.71, nu0=0.1, Ma=None, bulk_ratio=None, noise_seed=None,
            noise_amp=1e-6, prec="f32", nx=None, ny=None) -> dict:
     """Differentially heated square cavity (Sec. 4.3) in lattice units.
 
-    T0 = rho0 = 1, ideal gas with R = c_s^2/T0; L = N - 1; buoyancy velocity
-    U = Ma c_s, g = U^2 / (2 eps L), mu0 = rho0 U L sqrt(Pr / Ra) so that
-    Ra = Pr g rho0^2 (T_h - T_c) L^3 / (T0 mu0^2); Sutherland S = 110.5/600.
+    T0 = rho0 = 1, ideal gas with R = c_s^2/T0, L = N - 1, Sutherland
+    S = 110.5/600, first-order extrapolation, walls x = 0 at T0 (1 + eps) and
+    x = L at T0 (1 - eps), adiabatic top and bottom, gravity -y per unit mass.
+    The lattice viscosity is set by nu0 = mu0/rho0 (default 0.1, i.e. the
+    paper's tau = 0.8); gravity then follows from
+    Ra = Pr g rho0^2 (T_h - T_c) L^3 / (T0 mu0^2).  Passing Ma instead fixes
+    the buoyancy velocity U = Ma c_s, g = U^2/(2 eps L), mu0 = rho0 U L sqrt(Pr/Ra).
     """
     nx = N if nx is None else nx
     ny = N if ny is None else ny
     L = N - 1
-    U = Ma * math.sqrt(CS2)
-    g = U * U / (2.0 * eps * L)
-    mu0 = U * L * math.sqrt(Pr / Ra)
+    if Ma is not None:
+        U = Ma * math.sqrt(CS2)
+        g = U * U / (2.0 * eps * L)
+        nu0 = U * L * math.sqrt(Pr / Ra)
+    else:
+        g = Ra * nu0 * nu0 / (2.0 * eps * Pr * L ** 3)
     br = bulk_ratio_for_ra(Ra) if bulk_ratio is None else bulk_ratio
-    c = base_case(nx=nx, ny=ny, eos="ideal", Pr=Pr, gamma=1.4, nu0=mu0, bulk_ratio=br,
+    c = base_case(nx=nx, ny=ny, eos="ideal", Pr=Pr, gamma=1.4, nu0=nu0, bulk_ratio=br,
                   visc_law="sutherland", suth_S=110.5 / 600.0,
                   force=(0.0, -g), per_mass=True,
                   sides=[_side(T=1.0 + eps), _side(T=1.0 - eps),
                          _side(thermal="adiabatic"), _side(thermal="adiabatic")],
                   extrap_order=1, prec=prec)
-    c["Ra"], c["eps"], c["Ma"] = Ra, eps, Ma
+    c["Ra"], c["eps"] = Ra, eps
+    # Mach number of the reference velocity sqrt(Ra) mu0 / (rho0 L) of Sec. 4.3
+    c["Ma_ref"] = math.sqrt(Ra) * nu0 / L / math.sqrt(CS2)
     if noise_seed is not None:
         c["init"] = {"rho": 1.0 + noise_amp * noise(noise_seed, nx * ny).reshape(ny, nx)}
     return c
 
 
-def batch_cases(seed=2, n=64, Ma=0.05, prec="f32") -> list:
+def batch_cases(seed=2, n=64, nu0=0.1, prec="f32") -> list:
     """Uneven cavities: N in {128,256,512,1024}, log10 Ra in U[3,8],
     eps in U[0.1,0.6], Pr in {0.71,1,7}; four draws per case from one stream."""
     u = uniform01(seed, 4 * n).reshape(n, 4)
@@ -145,7 +154,7 @@ def batch_cases(seed=2, n=64, Ma=0.05, prec="f32") -> list:
         Ra = 10.0 ** (3.0 + 5.0 * u[k, 1])
         eps = 0.1 + 0.5 * u[k, 2]
         Pr = prs[min(int(u[k, 3] * 3), 2)]
-        out.append(cavity(N=N, Ra=Ra, eps=eps, Pr=Pr, Ma=Ma, prec=prec))
+        out.append(cavity(N=N, Ra=Ra, eps=eps, Pr=Pr, nu0=nu0, prec=prec))
     return out
 
 
