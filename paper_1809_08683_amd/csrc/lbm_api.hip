@@ -16,6 +16,7 @@
 namespace lbm {
 int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
                 int export_macros, hipStream_t stream);
+int step_blocks_per_cu(int prec);
 int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
                 int parity, hipStream_t stream);
 int launch_totals(const CaseParams* d_cases, int case_id, double* d_partial, int nblocks, double* d_out,
@@ -69,8 +70,9 @@ struct lbm_ctx {
     std::vector<lbm::CaseParams> P;
     std::vector<CaseHost> H;
     lbm::CaseParams* d_P = nullptr;
-    std::vector<lbm::WorkItem> work;
+    std::vector<lbm::WorkItem> work;     // one entry per wavefront slot of the launch
     lbm::WorkItem* d_work = nullptr;
+    long long n_items = 0;               // non-empty entries
     double* d_red = nullptr;
     std::vector<void*> allocs;
     hipStream_t stream = nullptr;
@@ -235,34 +237,65 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
 
 }
 
-int auto_seg_rows(int rows, int strips)
+// Work decomposition of one step.  Wall nodes go 64 per wavefront.  The
+// off-wall region of every case is cut into strips of 62 columns and each
+// strip into segments of nearly equal height; by default the number of
+// segments is chosen so that all items of a step are resident at once
+// (one round of wavefronts, no tail).  Slots are then laid out so that
+// block b runs on XCD b % 8 with a contiguous band of rows, wall items
+// first.
+void build_work(lbm_ctx* c, int seg_rows, long long capacity)
 {
-    // about 4096 interior wavefronts per case at large sizes
-    long long per = (long long)rows * strips / 4096;
-    return int(std::max<long long>(4, std::min<long long>(64, per)));
-}
-
-void build_work(lbm_ctx* c, int seg_rows)
-{
-    c->work.clear();
     const int nc = int(c->P.size());
+    std::vector<lbm::WorkItem> wall, inner;
+    long long total_cells = 0;   // strip-rows over all cases
     for (int k = 0; k < nc; ++k) {
         const auto& P = c->P[k];
         int nw = 0;
         if (P.wall_y) nw += 2 * P.nx;
         if (P.wall_x) nw += 2 * (P.wall_y ? P.ny - 2 : P.ny);
-        for (int b = 0; b < nw; b += 64) c->work.push_back({k, 1, b, 0, std::min(64, nw - b), 0});
+        for (int b = 0; b < nw; b += 64) wall.push_back({k, 1, b, 0, std::min(64, nw - b), 0});
+        const int xr = P.wall_x ? P.nx - 2 : P.nx, yr = P.wall_y ? P.ny - 2 : P.ny;
+        total_cells += (long long)((xr + 61) / 62) * yr;
     }
+    const long long budget = std::max<long long>(capacity - (long long)wall.size(), 1);
     for (int k = 0; k < nc; ++k) {
         const auto& P = c->P[k];
         const int xlo = P.wall_x, xhi = P.wall_x ? P.nx - 1 : P.nx;
         const int ylo = P.wall_y, yhi = P.wall_y ? P.ny - 1 : P.ny;
-        const int strips = (xhi - xlo + 61) / 62;
-        const int H = seg_rows > 0 ? seg_rows : auto_seg_rows(yhi - ylo, strips);
-        for (int y0 = ylo; y0 < yhi; y0 += H)
-            for (int s = 0; s < strips; ++s)
-                c->work.push_back({k, 0, xlo + 62 * s, y0, std::min(H, yhi - y0), 0});
+        const int rows = yhi - ylo, strips = (xhi - xlo + 61) / 62;
+        int nseg;
+        if (seg_rows > 0) {
+            nseg = (rows + seg_rows - 1) / seg_rows;
+        } else {
+            // this case's share of the resident slots, segments of >= 4 rows
+            const double share = double(strips) * rows / double(total_cells) * double(budget);
+            nseg = int(std::max(1.0, std::floor(share / strips)));
+            nseg = std::min(nseg, std::max(1, rows / 4));
+        }
+        for (int g = 0; g < nseg; ++g) {
+            const int y0 = ylo + int((long long)rows * g / nseg);
+            const int y1 = ylo + int((long long)rows * (g + 1) / nseg);
+            if (y1 <= y0) continue;
+            for (int st = 0; st < strips; ++st) inner.push_back({k, 0, xlo + 62 * st, y0, y1 - y0, 0});
+        }
     }
+    // bands: XCD-major slots, wall items spread over the bands first
+    constexpr int NX = 8;
+    std::vector<std::vector<lbm::WorkItem>> band(NX);
+    for (size_t i = 0; i < wall.size(); ++i) band[i % NX].push_back(wall[i]);
+    for (size_t i = 0; i < inner.size(); ++i) band[i * NX / inner.size()].push_back(inner[i]);
+    size_t longest = 0;
+    for (auto& b : band) longest = std::max(longest, b.size());
+    const size_t per_block = 4;
+    const size_t blocks_per_band = (longest + per_block - 1) / per_block;
+    c->work.assign(blocks_per_band * NX * per_block, lbm::WorkItem{0, 2, 0, 0, 0, 0});
+    for (int k = 0; k < NX; ++k)
+        for (size_t j = 0; j < band[k].size(); ++j) {
+            const size_t blk = (j / per_block) * NX + k;
+            c->work[blk * per_block + j % per_block] = band[k][j];
+        }
+    c->n_items = (long long)(wall.size() + inner.size());
 }
 
 lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* eos, const double* Pr,
@@ -318,7 +351,11 @@ lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* 
         c->H[k].base = base + off;
         off += L[k].total;
     }
-    build_work(c, opt[0].seg_rows);
+    int cus = 0;
+    HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
+    const int bpc = lbm::step_blocks_per_cu(c->prec);
+    const long long capacity = (long long)std::max(cus, 1) * std::max(bpc, 1) * 4;
+    build_work(c, opt[0].seg_rows, capacity);
     void* p = nullptr;
     HIP_TRY(c, hipMalloc(&p, sizeof(lbm::CaseParams) * ncases));
     c->allocs.push_back(p);
@@ -422,7 +459,7 @@ lbm_status lbm_batch_create(int ncases, const int* nx, const int* ny, const lbm_
 
 int lbm_batch_size(const lbm_ctx* c) { return c ? int(c->P.size()) : 0; }
 
-long long lbm_work_items(const lbm_ctx* c) { return c ? (long long)c->work.size() : 0; }
+long long lbm_work_items(const lbm_ctx* c) { return c ? c->n_items : 0; }
 
 lbm_status lbm_case_init(lbm_ctx* c, int k, const double* rho, const double* ux, const double* uy, const double* T)
 {

@@ -44,9 +44,25 @@ constexpr double cR88 = 6.0 * b;                                        // * s_p
 // ---------------------------------------------------------------------------
 // small numeric helpers, specialised per compute type
 // ---------------------------------------------------------------------------
+// FP64 reciprocal: hardware estimate refined by two Newton steps (relative
+// error at the level of the last bit, without the IEEE division sequence)
+__device__ __forceinline__ double rcp_d(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return r;
+}
+
 template <typename C> __device__ __forceinline__ C rcp(C x);
-template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ double rcp<double>(double x) { return rcp_d(x); }
 template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// pointers into global memory (lets the compiler use global, not flat, loads)
+template <typename T> using gconst = const __attribute__((address_space(1))) T;
+template <typename T> using gmut = __attribute__((address_space(1))) T;
+template <typename T> __device__ __forceinline__ gconst<T>* as_global(const void* p) { return (gconst<T>*)p; }
+template <typename T> __device__ __forceinline__ gmut<T>* as_global_mut(void* p) { return (gmut<T>*)p; }
 
 template <typename C> __device__ __forceinline__ C sqrt_(C x);
 template <> __device__ __forceinline__ double sqrt_<double>(double x) { return __builtin_sqrt(x); }
@@ -117,13 +133,34 @@ __device__ __forceinline__ void from_moments(const C m[9], C f[9])
 // ---------------------------------------------------------------------------
 template <typename C>
 struct NodeState {
-    C rho, ux, uy, T;     // full values (nonlinear terms, rates)
+    C drho;               // rho - rho0
+    C ux, uy;             // velocity
     C jx, jy;             // rho u = sum e f + F/2, kept as computed (no rho * (j / rho) round trip)
-    double Td;            // T recovered in FP64 (reported / reduced)
-    C drho, dT, drhoE;    // rho - rho0, T - T0, rho E - rho0 C_v T0
+    C dT;                 // T - T0 (T recovered in FP64)
+    C drhoE;              // rho E - rho0 C_v T0
     C dp, deta;           // p - p0, eta - eta0
-    C p, H, Fx, Fy, qe;
+    C H;                  // E + p / rho
+    C inv_rho;            // 1 / rho
 };
+
+template <typename C> __device__ __forceinline__ C rho_of(const Coef<C>& K, const NodeState<C>& s) { return K.rho0 + s.drho; }
+template <typename C> __device__ __forceinline__ C T_of(const Coef<C>& K, const NodeState<C>& s) { return K.T0 + s.dT; }
+
+// external force F (per unit volume, or rho * g per unit mass) and q_e = u.F
+template <typename C>
+struct Forcing {
+    C Fx, Fy, qe;
+};
+template <typename C>
+__device__ __forceinline__ Forcing<C> forcing(const Coef<C>& K, int per_mass, const NodeState<C>& s)
+{
+    Forcing<C> F;
+    const C rho = rho_of(K, s);
+    F.Fx = per_mass ? rho * K.fx : K.fx;
+    F.Fy = per_mass ? rho * K.fy : K.fy;
+    F.qe = s.ux * F.Fx + s.uy * F.Fy;
+    return F;
+}
 
 template <typename C>
 struct Rates {
@@ -151,110 +188,100 @@ __device__ __forceinline__ double eos_pressure_d(const Coef<C>& K, int eos, doub
 
 // p - p0: exact deviation forms for the linear-in-rho EOSs, FP64 otherwise
 template <typename C>
-__device__ __forceinline__ C eos_dp(const Coef<C>& K, int eos, C drho, C dT, C T, double rho_d, double T_d)
+__device__ __forceinline__ C eos_dp(const Coef<C>& K, int eos, C drho, C dT, double rho_d, double T_d)
 {
     if (eos == EOS_DECOUPLED) return K.R * K.T0 * drho;
-    if (eos == EOS_IDEAL) return K.R * (drho * T + K.rho0 * dT);   // R (rho T - rho0 T0)
+    if (eos == EOS_IDEAL) return K.R * (drho * (K.T0 + dT) + K.rho0 * dT);   // R (rho T - rho0 T0)
     return C(eos_pressure_d<C>(K, eos, rho_d, T_d) - K.p0_d);
 }
 
-// Completes a state from rho, u, T, rho E and their deviations (force, q_e,
-// p, eta, H).  eta = [p / c_s^2 - (2 + alpha1) rho] / beta1 (end of Sec. 2.2).
+// Completes a state from rho, u, T, E (force, p, eta, H).
+// eta = [p / c_s^2 - (2 + alpha1) rho] / beta1 (end of Sec. 2.2).
 template <typename C>
-__device__ __forceinline__ void complete_state(const Coef<C>& K, int eos, int per_mass,
-                                               NodeState<C>& s, C inv_rho, double rho_d, double rhoE_d)
+__device__ __forceinline__ void complete_state(const Coef<C>& K, int eos, NodeState<C>& s, double rho_d,
+                                               double T_d, double E_d)
 {
-    s.Fx = per_mass ? s.rho * K.fx : K.fx;
-    s.Fy = per_mass ? s.rho * K.fy : K.fy;
-    s.qe = s.ux * s.Fx + s.uy * s.Fy;
-    s.dp = eos_dp<C>(K, eos, s.drho, s.dT, s.T, rho_d, s.Td);
-    s.p = C(K.p0_d) + s.dp;
+    s.dp = eos_dp<C>(K, eos, s.drho, s.dT, rho_d, T_d);
     s.deta = (C(3) * s.dp - C(2.0 + mc::alpha1) * s.drho) * C(1.0 / mc::beta1);
-    s.H = C((rhoE_d + double(s.p)) / rho_d);   // H = E + p/rho
-    (void)inv_rho;
+    s.H = C(E_d) + (C(K.p0_d) + s.dp) * s.inv_rho;   // H = E + p/rho
 }
 
 // Interior node: rho = sum f, rho u = sum e f + F/2 (eq. rho.u),
 // rho E = sum g + q_e/2 (eq. E), T = (E - |u|^2/2)/C_v with E and the
 // subtraction carried out in FP64.  dm = M (f - f_rest), dn0 = sum (g - g_rest).
+// Returns T in FP64.
 template <typename C>
-__device__ __forceinline__ C state_from_moments(const Coef<C>& K, int eos, int per_mass,
-                                                const C dm[9], C dn0, NodeState<C>& s)
+__device__ __forceinline__ double state_from_moments(const Coef<C>& K, int eos, int per_mass,
+                                                     const C dm[9], C dn0, NodeState<C>& s)
 {
     s.drho = dm[0];
-    s.rho = K.rho0 + s.drho;
-    const C inv_rho = rcp<C>(s.rho);
-    const C Fx = per_mass ? s.rho * K.fx : K.fx;
-    const C Fy = per_mass ? s.rho * K.fy : K.fy;
+    const C rho = K.rho0 + s.drho;
+    s.inv_rho = rcp<C>(rho);
+    const C Fx = per_mass ? rho * K.fx : K.fx;
+    const C Fy = per_mass ? rho * K.fy : K.fy;
     s.jx = dm[3] + C(0.5) * Fx;
     s.jy = dm[5] + C(0.5) * Fy;
-    s.ux = s.jx * inv_rho;
-    s.uy = s.jy * inv_rho;
-    const C qe = s.ux * Fx + s.uy * Fy;
-    s.drhoE = dn0 + C(0.5) * qe;
+    s.ux = s.jx * s.inv_rho;
+    s.uy = s.jy * s.inv_rho;
+    s.drhoE = dn0 + C(0.5) * (s.ux * Fx + s.uy * Fy);
     const double rho_d = K.rho0_d + double(s.drho);
-    const double rhoE_d = K.rhoE0_d + double(s.drhoE);
     const double uxd = double(s.ux), uyd = double(s.uy);
-    s.Td = (rhoE_d / rho_d - 0.5 * (uxd * uxd + uyd * uyd)) * K.inv_cv_d;
-    s.T = C(s.Td);
-    s.dT = C(s.Td - K.T0_d);
-    complete_state<C>(K, eos, per_mass, s, inv_rho, rho_d, rhoE_d);
-    return inv_rho;
+    const double E_d = (K.rhoE0_d + double(s.drhoE)) * rcp_d(rho_d);
+    const double T_d = (E_d - 0.5 * (uxd * uxd + uyd * uyd)) * K.inv_cv_d;
+    s.dT = C(T_d - K.T0_d);
+    complete_state<C>(K, eos, s, rho_d, T_d, E_d);
+    return T_d;
 }
 
 // Wall node (Sec. 3.1): rho from the bounce-back-completed DFs, u prescribed,
 // T prescribed (Dirichlet) or from rho E = sum g + q_e/2 (adiabatic).
 template <typename C>
-__device__ __forceinline__ C state_wall(const Coef<C>& K, int eos, int per_mass,
-                                        C drho, C dn0, C ubx, C uby, int adiabatic, double Tw,
-                                        NodeState<C>& s)
+__device__ __forceinline__ double state_wall(const Coef<C>& K, int eos, int per_mass,
+                                             C drho, C dn0, C ubx, C uby, int adiabatic, double Tw,
+                                             NodeState<C>& s)
 {
     s.drho = drho;
-    s.rho = K.rho0 + drho;
-    const C inv_rho = rcp<C>(s.rho);
+    const C rho = K.rho0 + drho;
+    s.inv_rho = rcp<C>(rho);
     s.ux = ubx;
     s.uy = uby;
-    s.jx = s.rho * ubx;
-    s.jy = s.rho * uby;
-    const C Fx = per_mass ? s.rho * K.fx : K.fx;
-    const C Fy = per_mass ? s.rho * K.fy : K.fy;
+    s.jx = rho * ubx;
+    s.jy = rho * uby;
+    const C Fx = per_mass ? rho * K.fx : K.fx;
+    const C Fy = per_mass ? rho * K.fy : K.fy;
     const double rho_d = K.rho0_d + double(drho);
     const double u2 = double(ubx) * double(ubx) + double(uby) * double(uby);
-    double rhoE_d;
+    double E_d, T_d;
     if (adiabatic) {
         s.drhoE = dn0 + C(0.5) * (ubx * Fx + uby * Fy);
-        rhoE_d = K.rhoE0_d + double(s.drhoE);
-        s.Td = (rhoE_d / rho_d - 0.5 * u2) * K.inv_cv_d;
+        E_d = (K.rhoE0_d + double(s.drhoE)) * rcp_d(rho_d);
+        T_d = (E_d - 0.5 * u2) * K.inv_cv_d;
     } else {
-        s.Td = Tw;
-        rhoE_d = rho_d * (K.cv_d * Tw + 0.5 * u2);
-        s.drhoE = C(rhoE_d - K.rhoE0_d);
+        T_d = Tw;
+        E_d = K.cv_d * Tw + 0.5 * u2;
+        s.drhoE = C(rho_d * E_d - K.rhoE0_d);
     }
-    s.T = C(s.Td);
-    s.dT = C(s.Td - K.T0_d);
-    complete_state<C>(K, eos, per_mass, s, inv_rho, rho_d, rhoE_d);
-    return inv_rho;
+    s.dT = C(T_d - K.T0_d);
+    complete_state<C>(K, eos, s, rho_d, T_d, E_d);
+    return T_d;
 }
 
 // Prescribed state (initial fields): E = C_v T + |u|^2/2.
 template <typename C>
-__device__ __forceinline__ C state_prescribed(const Coef<C>& K, int eos, int per_mass,
-                                              double rho_d, double ux, double uy, double T_d, NodeState<C>& s)
+__device__ __forceinline__ double state_prescribed(const Coef<C>& K, int eos, double rho_d, double ux, double uy,
+                                                   double T_d, NodeState<C>& s)
 {
     s.drho = C(rho_d - K.rho0_d);
-    s.rho = C(rho_d);
+    s.inv_rho = rcp<C>(C(rho_d));
     s.ux = C(ux);
     s.uy = C(uy);
     s.jx = C(rho_d * ux);
     s.jy = C(rho_d * uy);
-    s.Td = T_d;
-    s.T = C(T_d);
     s.dT = C(T_d - K.T0_d);
-    const double rhoE_d = rho_d * (K.cv_d * T_d + 0.5 * (ux * ux + uy * uy));
-    s.drhoE = C(rhoE_d - K.rhoE0_d);
-    const C inv_rho = rcp<C>(s.rho);
-    complete_state<C>(K, eos, per_mass, s, inv_rho, rho_d, rhoE_d);
-    return inv_rho;
+    const double E_d = K.cv_d * T_d + 0.5 * (ux * ux + uy * uy);
+    s.drhoE = C(rho_d * E_d - K.rhoE0_d);
+    complete_state<C>(K, eos, s, rho_d, T_d, E_d);
+    return T_d;
 }
 
 // Local relaxation rates (Sec. 4): nu = mu(T)/rho = c_s^2 (1/s_p - 1/2);
@@ -262,8 +289,9 @@ __device__ __forceinline__ C state_prescribed(const Coef<C>& K, int eos, int per
 // ratio * nu; lambda = C_p mu / Pr = kappa rho0 C_p (1/sigma_j - 1/2);
 // (1/sigma_j - 1/2)(1/sigma_e - 1/2) = 1/4.
 template <typename C>
-__device__ __forceinline__ void local_rates(const Coef<C>& K, int visc_law, C rho, C rho_inv, C T, Rates<C>& r)
+__device__ __forceinline__ void local_rates(const Coef<C>& K, int visc_law, const NodeState<C>& s, Rates<C>& r)
 {
+    const C rho = rho_of(K, s), rho_inv = s.inv_rho, T = T_of(K, s);
     C mu;
     if (visc_law == VISC_CONST) {
         mu = K.mu0;
@@ -316,9 +344,9 @@ __device__ __forceinline__ void meq_f(const NodeState<C>& s, C q[9])
 
 // F_m of Sec. 2.1; rows 0, 3, 5 are 0, F_x, F_y
 template <typename C>
-__device__ __forceinline__ void force_moments(const NodeState<C>& s, C q[9])
+__device__ __forceinline__ void force_moments(const NodeState<C>& s, const Forcing<C>& F, C q[9])
 {
-    const C ux = s.ux, uy = s.uy, Fx = s.Fx, Fy = s.Fy;
+    const C ux = s.ux, uy = s.uy, Fx = F.Fx, Fy = F.Fy;
     const C Fu = Fx * ux + Fy * uy;
     q[0] = C(0);
     q[1] = C(6) * Fu;
@@ -350,9 +378,9 @@ __device__ __forceinline__ void neq_g(const Coef<C>& K, const NodeState<C>& s, C
 
 // Q_m of Sec. 2.2
 template <typename C>
-__device__ __forceinline__ void source_moments(const NodeState<C>& s, C q[9])
+__device__ __forceinline__ void source_moments(const NodeState<C>& s, const Forcing<C>& F, C q[9])
 {
-    const C qe = s.qe;
+    const C qe = F.qe;
     q[0] = qe;
     q[1] = C(mc::gamma1) * qe;
     q[2] = C(mc::gamma2) * qe;
@@ -526,20 +554,43 @@ __device__ __forceinline__ void nonequilibrium(const NodeState<C>& s, const Rate
 // storage codecs of the DF deviations: FP64, FP32, FP16 (FP32 arithmetic)
 // ---------------------------------------------------------------------------
 template <typename S> struct Store;
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 0
+#endif
+#ifndef LBM_NT_LOAD
+#define LBM_NT_LOAD 0
+#endif
+template <typename T> __device__ __forceinline__ T ld(const T* p)
+{
+    if constexpr (LBM_NT_LOAD) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <typename T> __device__ __forceinline__ void st(T* p, T v)
+{
+    if constexpr (LBM_NT_STORE) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 template <> struct Store<double> {
     using C = double;
-    static __device__ __forceinline__ double load(const double* p) { return *p; }
-    static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
+    static __device__ __forceinline__ double load(const double* p) { return ld(p); }
+    static __device__ __forceinline__ void store(double* p, double v) { st(p, v); }
 };
 template <> struct Store<float> {
     using C = float;
-    static __device__ __forceinline__ float load(const float* p) { return *p; }
-    static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
+    static __device__ __forceinline__ float load(const float* p) { return ld(p); }
+    static __device__ __forceinline__ void store(float* p, float v) { st(p, v); }
 };
 template <> struct Store<__half> {
     using C = float;
-    static __device__ __forceinline__ float load(const __half* p) { return __half2float(*p); }
-    static __device__ __forceinline__ void store(__half* p, float v) { *p = __float2half_rn(v); }
+    static __device__ __forceinline__ float load(const __half* p)
+    {
+        const unsigned short b = ld(reinterpret_cast<const unsigned short*>(p));
+        return __half2float(__ushort_as_half(b));
+    }
+    static __device__ __forceinline__ void store(__half* p, float v)
+    {
+        st(reinterpret_cast<unsigned short*>(p), __half_as_ushort(__float2half_rn(v)));
+    }
 };
 
 }  // namespace lbm

@@ -60,8 +60,8 @@ __device__ __forceinline__ int side_y(const CaseParams& P, int y)
 // The x-wall sets the velocity of a corner and its temperature when it is
 // Dirichlet; otherwise a Dirichlet y-wall sets the temperature.
 template <typename C>
-__device__ __forceinline__ C node_state(const CaseParams& P, const Coef<C>& K, int sx, int sy,
-                                        const C m[9], C n0, NodeState<C>& s)
+__device__ __forceinline__ double node_state(const CaseParams& P, const Coef<C>& K, int sx, int sy,
+                                             const C m[9], C n0, NodeState<C>& s)
 {
     if (sx < 0 && sy < 0) return state_from_moments<C>(K, P.eos, P.per_mass, m, n0, s);
     const int sv = sx >= 0 ? sx : sy;
@@ -118,39 +118,94 @@ __device__ __forceinline__ void store_ghosts(const CaseParams& P, S* dst, int x,
 }
 
 template <typename C>
-__device__ __forceinline__ void export_node(const CaseParams& P, int x, int y, const NodeState<C>& s)
+__device__ __forceinline__ void export_node(const CaseParams& P, int x, int y, const NodeState<C>& s, double T_d)
 {
+    const Coef<C>& K = coef<C>(P);
     const long long nn = (long long)P.nx * P.ny;
     const long long i = (long long)y * P.nx + x;
-    P.macro[i] = coef<C>(P).rho0_d + double(s.drho);
+    const double rho = K.rho0_d + double(s.drho);
+    P.macro[i] = rho;
     P.macro[nn + i] = double(s.ux);
     P.macro[2 * nn + i] = double(s.uy);
-    P.macro[3 * nn + i] = s.Td;
-    P.macro[4 * nn + i] = coef<C>(P).p0_d + double(s.dp);
-    const bool ok = s.rho > C(0) && s.Td > 0.0 && s.rho < C(1e30) && s.Td < 1e30 &&
-                    s.ux == s.ux && s.uy == s.uy && s.p == s.p;
+    P.macro[3 * nn + i] = T_d;
+    P.macro[4 * nn + i] = K.p0_d + double(s.dp);
+    const bool ok = rho > 0.0 && T_d > 0.0 && rho < 1e30 && T_d < 1e30 && s.ux == s.ux && s.uy == s.uy &&
+                    s.dp == s.dp;
     if (!ok) atomicOr(P.flag, 1);
 }
 
 // ---------------------------------------------------------------------------
-// collision of a node given its pulled moments
+// collision of an off-wall node given its pulled moments, written so that
+// the temporaries of the f part are dead before the g part starts:
+//   N = m - m^eq + F_m/2, Ntil = (I - S/2) N,
+//   mbar = 2 m^eq - m + 2 Ntil - [R Ntil + T.grad rho + X.grad p]
+//   (eq. LBE.u.c with m = m^eq - F_m/2 + N), conserved rows mbar_0 = m_0,
+//   mbar_3 = m_3 + F_x, mbar_5 = m_5 + F_y;
+//   H = n - n^eq + Q_m/2, Htil = (I - L/2) H (App. C steps 1-3),
+//   nbar = 2 n^eq - n + 2 Htil + Y [(m + mbar)/2 - m^eq] (eq. LBE.T.c,
+//   App. C step 4), conserved row nbar_0 = n_0 + q_e.
+// The f and g post-collision deviations go to fb and gb.
 // ---------------------------------------------------------------------------
 template <typename C>
 __device__ __forceinline__ void collide_interior(const CaseParams& P, const Coef<C>& K, const NodeState<C>& s,
-                                                 C inv_rho, const C m[9], const C n[9],
+                                                 const C m[9], const C n[9],
                                                  C gr_x, C gr_y, C gp_x, C gp_y, C fb[9], C gb[9])
 {
     Rates<C> r;
-    local_rates<C>(K, P.visc_law, s.rho, inv_rho, s.T, r);
-    C meq[9], Fm[9], neq[9], Qm[9], N[9], Nt[9], Hm[9], Ht[9], mb[9], nb[9];
-    meq_f<C>(s, meq);
-    force_moments<C>(s, Fm);
-    neq_g<C>(K, s, neq);
-    source_moments<C>(s, Qm);
-    nonequilibrium<C>(s, r, m, n, meq, Fm, neq, Qm, N, Nt, Hm, Ht);
-    post_collision<C>(s, r, P.cubic, meq, Fm, N, Nt, neq, Qm, Hm, Ht, gr_x, gr_y, gp_x, gp_y, mb, nb);
-    from_moments<C>(mb, fb);
-    from_moments<C>(nb, gb);
+    local_rates<C>(K, P.visc_law, s, r);
+    const Forcing<C> F = forcing<C>(K, P.per_mass, s);
+    C G1, G7, G8;
+    {
+        C meq[9], N[9], Nt[9], mb[9];
+        {
+            C Fm[9];
+            meq_f<C>(s, meq);
+            force_moments<C>(s, F, Fm);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) N[i] = m[i] - meq[i] + C(0.5) * Fm[i];
+            N[0] = C(0);
+            N[3] = C(0);
+            N[5] = C(0);
+        }
+        tilde_f<C>(s, r, N, Nt);
+        C c1, c7, c8;
+        corrections<C>(s, r, P.cubic, Nt, gr_x, gr_y, gp_x, gp_y, c1, c7, c8);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) mb[i] = C(2) * meq[i] - m[i] + C(2) * Nt[i];
+        mb[0] = m[0];
+        mb[3] = m[3] + F.Fx;
+        mb[5] = m[5] + F.Fy;
+        mb[1] -= c1;
+        mb[7] -= c7;
+        mb[8] -= c8;
+        // (m + mbar)/2 - m^eq on rows 1, 7, 8
+        G1 = Nt[1] - C(0.5) * c1;
+        G7 = Nt[7] - C(0.5) * c7;
+        G8 = Nt[8] - C(0.5) * c8;
+        from_moments<C>(mb, fb);
+    }
+    {
+        C neq[9], Hm[9], Ht[9], nb[9];
+        {
+            C Qm[9];
+            neq_g<C>(K, s, neq);
+            source_moments<C>(s, F, Qm);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Hm[i] = n[i] - neq[i] + C(0.5) * Qm[i];
+            Hm[0] = C(0);
+        }
+        tilde_g<C>(r, Hm, Ht);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) nb[i] = C(2) * neq[i] - n[i] + C(2) * Ht[i];
+        nb[0] = n[0] + F.qe;
+        const C y3 = s.ux * (C(1.0 / 3.0) * G1 + G7) + C(2) * s.uy * G8;
+        const C y5 = s.uy * (C(1.0 / 3.0) * G1 - G7) + C(2) * s.ux * G8;
+        nb[3] += y3;
+        nb[4] -= y3;
+        nb[5] += y5;
+        nb[6] -= y5;
+        from_moments<C>(nb, gb);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -161,60 +216,90 @@ __device__ __forceinline__ C from_left(C v) { return __shfl_up(v, 1, WAVE); }
 template <typename C>
 __device__ __forceinline__ C from_right(C v) { return __shfl_down(v, 1, WAVE); }
 
+// stored row (0 .. ny+1) of lattice row v in [-1, ny], wrapped on a periodic axis
+__device__ __forceinline__ int stored_row(int v, int n, int walled)
+{
+    if (!walled) v = v < 0 ? v + n : (v >= n ? v - n : v);
+    return v + 1;
+}
+
+// Pull the 18 DF deviations of one lattice row into registers.  rb[k]
+// points at stored row (y - 1 + k) of plane 0; col[k] is the stored column
+// of x - 1 + k.  A DF moving along e comes from (x - e_x, y - e_y).
 template <typename S>
-__device__ void interior_item(const CaseParams& P, const WorkItem& w, const S* __restrict__ src,
-                              S* __restrict__ dst, int export_macros)
+__device__ __forceinline__ void pull_row_raw(gconst<S>* const rb[3], const int col[3], int plane,
+                                             typename Store<S>::C f[9], typename Store<S>::C g[9])
+{
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        gconst<S>* base = rb[1 - EYq(q)] + q * plane;
+        const int c = col[1 - EXq(q)];
+        f[q] = Store<S>::load((const S*)(base + c));
+        g[q] = Store<S>::load((const S*)(base + 9 * plane + c));
+    }
+}
+
+template <typename S>
+__device__ void interior_item(const CaseParams& P, const WorkItem& w, gconst<S>* __restrict__ src,
+                              gmut<S>* __restrict__ dst, int export_macros)
 {
     using C = typename Store<S>::C;
     const Coef<C>& K = coef<C>(P);
     const int lane = threadIdx.x & (WAVE - 1);
-    const int xhi = P.wall_x ? P.nx - 1 : P.nx;
+    const int nx = P.nx, ny = P.ny, pitch = P.pitch, plane = int(P.plane);
+    const int wall_x = P.wall_x, wall_y = P.wall_y;
+    const int xhi = wall_x ? nx - 1 : nx;
     const int x = w.x0 - 1 + lane;
     const bool out_lane = lane >= 1 && lane <= STRIP && x < xhi;
     const int xc = min(x, xhi);                    // lanes past the halo mirror a valid node
-    const int sx = side_x(P, xc);
+    const int sx = side_x(P, wrap_axis(xc, nx, wall_x));
+    int col[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) col[k] = wrap_axis(xc - 1 + k, nx, wall_x) + 1;
+
+    auto row_ptrs = [&](int yy, gconst<S>* rb[3]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rb[k] = src + stored_row(yy - 1 + k, ny, wall_y) * pitch;
+    };
+    // moments and state of a pulled row
+    auto row_state = [&](int yy, const C f[9], const C g[9], C dm[9], C dn[9], NodeState<C>& st) -> double {
+        to_moments<C>(f, dm);
+        to_moments<C>(g, dn);
+        const int yw = stored_row(yy, ny, wall_y) - 1;
+        return node_state<C>(P, K, sx, side_y(P, yw), dm, dn[0], st);
+    };
 
     C m_c[9], n_c[9], m_n[9], n_n[9];
     NodeState<C> s_c, s_n;
-    C inv_c = C(0), inv_n = C(0);
-    C rho_m = C(0), p_m = C(0);
-
-    auto pull_row = [&](int yy, C mm[9], C nn[9]) {
-        const long long rows[3] = {
-            (long long)(wrap_axis(yy - 1, P.ny, P.wall_y) + 1) * P.pitch,   // source y - 1 (e_y = +1)
-            (long long)(wrap_axis(yy, P.ny, P.wall_y) + 1) * P.pitch,       // e_y = 0
-            (long long)(wrap_axis(yy + 1, P.ny, P.wall_y) + 1) * P.pitch};  // e_y = -1
-        C f[9], g[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const long long idx = rows[1 - EYq(q)] + (wrap_axis(xc - EXq(q), P.nx, P.wall_x) + 1);
-            f[q] = Store<S>::load(src + q * P.plane + idx);
-            g[q] = Store<S>::load(src + (9 + q) * P.plane + idx);
-        }
-        to_moments<C>(f, mm);
-        to_moments<C>(g, nn);
-    };
-
+    C rho_m, p_m;
     const int y0 = w.y0;
-    // halo row below the segment: only rho and p are kept
     {
-        C mm[9], nn[9];
+        gconst<S>* rb[3];
+        C f[9], g[9], dm[9], dn[9];
         NodeState<C> st;
-        const int yy = y0 - 1;
-        pull_row(yy, mm, nn);
-        const int yw = wrap_axis(yy, P.ny, P.wall_y);
-        node_state<C>(P, K, sx, side_y(P, yw), mm, nn[0], st);
+        row_ptrs(y0 - 1, rb);
+        pull_row_raw<S>(rb, col, plane, f, g);
+        row_state(y0 - 1, f, g, dm, dn, st);
         rho_m = st.drho;
         p_m = st.dp;
+        row_ptrs(y0, rb);
+        pull_row_raw<S>(rb, col, plane, f, g);
+        row_state(y0, f, g, m_c, n_c, s_c);
+        row_ptrs(y0 + 1, rb);
+        pull_row_raw<S>(rb, col, plane, f, g);
+        row_state(y0 + 1, f, g, m_n, n_n, s_n);
     }
-    pull_row(y0, m_c, n_c);
-    inv_c = node_state<C>(P, K, sx, side_y(P, y0), m_c, n_c[0], s_c);
 
     for (int i = 0; i < w.len; ++i) {
         const int y = y0 + i;
-        const int yn = wrap_axis(y + 1, P.ny, P.wall_y);
-        pull_row(y + 1, m_n, n_n);
-        inv_n = node_state<C>(P, K, sx, side_y(P, yn), m_n, n_n[0], s_n);
+        const bool more = i + 1 < w.len;
+        // issue the loads of row y + 2 before the collision of row y
+        C fr[9], gr[9];
+        if (more) {
+            gconst<S>* rb[3];
+            row_ptrs(y + 2, rb);
+            pull_row_raw<S>(rb, col, plane, fr, gr);
+        }
 
         // isotropic gradients d_a phi = 3 sum_q w_q e_qa phi(x + e_q), taken on
         // the deviations rho - rho0 and p - p0
@@ -231,20 +316,24 @@ __device__ void interior_item(const CaseParams& P, const WorkItem& w, const S* _
 
         if (out_lane) {
             C fb[9], gb[9];
-            collide_interior<C>(P, K, s_c, inv_c, m_c, n_c, gr_x, gr_y, gp_x, gp_y, fb, gb);
-            const long long idx = (long long)(y + 1) * P.pitch + (x + 1);
-            store_node<S>(P, dst, idx, fb, gb);
-            if (export_macros) export_node<C>(P, x, y, s_c);
+            collide_interior<C>(P, K, s_c, m_c, n_c, gr_x, gr_y, gp_x, gp_y, fb, gb);
+            gmut<S>* o = dst + (y + 1) * pitch + (x + 1);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                Store<S>::store((S*)(o + q * plane), fb[q]);
+                Store<S>::store((S*)(o + (9 + q) * plane), gb[q]);
+            }
+            if (export_macros) export_node<C>(P, x, y, s_c, K.T0_d + double(s_c.dT));
         }
         rho_m = s_c.drho;
         p_m = s_c.dp;
         s_c = s_n;
-        inv_c = inv_n;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             m_c[q] = m_n[q];
             n_c[q] = n_n[q];
         }
+        if (more) row_state(y + 2, fr, gr, m_n, n_n, s_n);
     }
 }
 
@@ -331,14 +420,15 @@ __device__ __forceinline__ void tilde_at(const CaseParams& P, const S* src, int 
     C m[9], n[9];
     NodeState<C> s;
     pull_node<S, C>(P, src, x, y, m, n);
-    const C inv_rho = node_state<C>(P, K, -1, -1, m, n[0], s);
+    node_state<C>(P, K, -1, -1, m, n[0], s);
     Rates<C> r;
-    local_rates<C>(K, P.visc_law, s.rho, inv_rho, s.T, r);
+    local_rates<C>(K, P.visc_law, s, r);
+    const Forcing<C> F = forcing<C>(K, P.per_mass, s);
     C meq[9], Fm[9], neq[9], Qm[9], N[9], Hm[9];
     meq_f<C>(s, meq);
-    force_moments<C>(s, Fm);
+    force_moments<C>(s, F, Fm);
     neq_g<C>(K, s, neq);
-    source_moments<C>(s, Qm);
+    source_moments<C>(s, F, Qm);
     nonequilibrium<C>(s, r, m, n, meq, Fm, neq, Qm, N, Zm, Hm, Zn);
     const C y3 = s.ux * (C(1.0 / 3.0) * Zm[1] + Zm[7]) + C(2) * s.uy * Zm[8];
     const C y5 = s.uy * (C(1.0 / 3.0) * Zm[1] - Zm[7]) + C(2) * s.ux * Zm[8];
@@ -364,7 +454,7 @@ __device__ void wall_item(const CaseParams& P, const WorkItem& w, const S* __res
     C m[9], n[9];
     NodeState<C> s;
     pull_node<S, C>(P, src, xb, yb, m, n);
-    const C inv_rho = node_state<C>(P, K, sx, sy, m, n[0], s);
+    const double T_d = node_state<C>(P, K, sx, sy, m, n[0], s);
 
     // extrapolated tilde non-equilibrium moments (eq. neq.extrapolation)
     const int ndx = sx == 0 ? 1 : (sx == 1 ? -1 : 0);
@@ -387,7 +477,7 @@ __device__ void wall_item(const CaseParams& P, const WorkItem& w, const S* __res
 
     // invert with the wall node's own S, L, Y (App. B)
     Rates<C> r;
-    local_rates<C>(K, P.visc_law, s.rho, inv_rho, s.T, r);
+    local_rates<C>(K, P.visc_law, s, r);
     C N[9], Ht[9], Hm[9];
     untilde_f<C>(s, r, Zm, N);
     {
@@ -407,38 +497,47 @@ __device__ void wall_item(const CaseParams& P, const WorkItem& w, const S* __res
     wall_axis_gradient<S>(P, src, xb, yb, 0, s.drho, s.dp, gr_x, gp_x);
     wall_axis_gradient<S>(P, src, xb, yb, 1, s.drho, s.dp, gr_y, gp_y);
 
+    const Forcing<C> F = forcing<C>(K, P.per_mass, s);
     C meq[9], Fm[9], neq[9], Qm[9], mb[9], nb[9], fb[9], gb[9];
     meq_f<C>(s, meq);
-    force_moments<C>(s, Fm);
+    force_moments<C>(s, F, Fm);
     neq_g<C>(K, s, neq);
-    source_moments<C>(s, Qm);
+    source_moments<C>(s, F, Qm);
     post_collision<C>(s, r, P.cubic, meq, Fm, N, Zm, neq, Qm, Hm, Ht, gr_x, gr_y, gp_x, gp_y, mb, nb);
     from_moments<C>(mb, fb);
     from_moments<C>(nb, gb);
     const long long idx = (long long)(yb + 1) * P.pitch + (xb + 1);
     store_node<S>(P, dst, idx, fb, gb);
     store_ghosts<S>(P, dst, xb, yb, fb, gb);
-    if (export_macros) export_node<C>(P, xb, yb, s);
+    if (export_macros) export_node<C>(P, xb, yb, s, T_d);
 }
 
 // ---------------------------------------------------------------------------
-// step kernel
+// step kernel: one launch per time step.  The host lays the work list out
+// slot by slot (slot = block * WAVES_PER_BLOCK + wave) so that wall items
+// start first and each XCD's blocks cover one contiguous band of rows;
+// kind 2 marks an empty slot.
 // ---------------------------------------------------------------------------
+// Register budget per precision: FP32/FP16 storage fit 4 wavefronts per
+// SIMD (<= 128 VGPRs), FP64 fits 2.
+template <typename S> struct Occupancy { static constexpr int waves = 4; };
+template <> struct Occupancy<double> { static constexpr int waves = 2; };
+
 template <typename S>
-__global__ __launch_bounds__(WAVE * WAVES_PER_BLOCK) void step_kernel(
+__global__ __launch_bounds__(WAVE * WAVES_PER_BLOCK)
+__attribute__((amdgpu_waves_per_eu(Occupancy<S>::waves, 8))) void step_kernel(
     const CaseParams* __restrict__ cases, const WorkItem* __restrict__ work, int nwork, int parity,
     int export_macros)
 {
     const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6));
     if (wid >= nwork) return;
     const WorkItem w = work[wid];
+    if (w.kind == 2) return;
     const CaseParams& P = cases[w.case_id];
-    const S* src = static_cast<const S*>(P.buf[parity]);
-    S* dst = static_cast<S*>(P.buf[parity ^ 1]);
     if (w.kind == 0)
-        interior_item<S>(P, w, src, dst, export_macros);
+        interior_item<S>(P, w, as_global<S>(P.buf[parity]), as_global_mut<S>(P.buf[parity ^ 1]), export_macros);
     else
-        wall_item<S>(P, w, src, dst, export_macros);
+        wall_item<S>(P, w, static_cast<const S*>(P.buf[parity]), static_cast<S*>(P.buf[parity ^ 1]), export_macros);
 }
 
 // ---------------------------------------------------------------------------
@@ -447,12 +546,12 @@ __global__ __launch_bounds__(WAVE * WAVES_PER_BLOCK) void step_kernel(
 // the current source buffer (with ghost cells) and exported
 // ---------------------------------------------------------------------------
 template <typename C>
-__device__ __forceinline__ void init_state(const CaseParams& P, const Coef<C>& K, const double* fld, int x, int y,
-                                           NodeState<C>& s, C& inv_rho)
+__device__ __forceinline__ double init_state(const CaseParams& P, const Coef<C>& K, const double* fld, int x, int y,
+                                             NodeState<C>& s)
 {
     const long long nn = (long long)P.nx * P.ny;
     const long long i = (long long)y * P.nx + x;
-    inv_rho = state_prescribed<C>(K, P.eos, P.per_mass, fld[i], fld[nn + i], fld[2 * nn + i], fld[3 * nn + i], s);
+    return state_prescribed<C>(K, P.eos, fld[i], fld[nn + i], fld[2 * nn + i], fld[3 * nn + i], s);
 }
 
 template <typename C>
@@ -477,8 +576,7 @@ __global__ __launch_bounds__(256) void init_kernel(const CaseParams* __restrict_
     if (gid >= (long long)P.nx * P.ny) return;
     const int x = int(gid % P.nx), y = int(gid / P.nx);
     NodeState<C> s;
-    C inv_rho;
-    init_state<C>(P, K, fld, x, y, s, inv_rho);
+    const double T_d = init_state<C>(P, K, fld, x, y, s);
     const int sx = side_x(P, x), sy = side_y(P, y);
     C gr[2], gp[2];
     if (sx < 0 && sy < 0) {
@@ -519,14 +617,15 @@ __global__ __launch_bounds__(256) void init_kernel(const CaseParams* __restrict_
         }
     }
     Rates<C> r;
-    local_rates<C>(K, P.visc_law, s.rho, inv_rho, s.T, r);
+    local_rates<C>(K, P.visc_law, s, r);
+    const Forcing<C> F = forcing<C>(K, P.per_mass, s);
     C meq[9], Fm[9], neq[9], Qm[9], Z[9], mb[9], nb[9], fb[9], gb[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) Z[q] = C(0);
     meq_f<C>(s, meq);
-    force_moments<C>(s, Fm);
+    force_moments<C>(s, F, Fm);
     neq_g<C>(K, s, neq);
-    source_moments<C>(s, Qm);
+    source_moments<C>(s, F, Qm);
     post_collision<C>(s, r, P.cubic, meq, Fm, Z, Z, neq, Qm, Z, Z, gr[0], gr[1], gp[0], gp[1], mb, nb);
     from_moments<C>(mb, fb);
     from_moments<C>(nb, gb);
@@ -534,7 +633,7 @@ __global__ __launch_bounds__(256) void init_kernel(const CaseParams* __restrict_
     const long long idx = (long long)(y + 1) * P.pitch + (x + 1);
     store_node<S>(P, dst, idx, fb, gb);
     if (sx >= 0 || sy >= 0) store_ghosts<S>(P, dst, x, y, fb, gb);
-    export_node<C>(P, x, y, s);
+    export_node<C>(P, x, y, s, T_d);
 }
 
 // ---------------------------------------------------------------------------
@@ -664,9 +763,9 @@ int launch_copy(const void* src, void* dst, long long bytes, hipStream_t stream)
 int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
                 int export_macros, hipStream_t stream)
 {
-    const int blocks = (nwork + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-    if (blocks == 0) return 0;
-    const dim3 grid(blocks), block(WAVE * WAVES_PER_BLOCK);
+    const dim3 block(WAVE * WAVES_PER_BLOCK);
+    const dim3 grid((nwork + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
+    if (nwork == 0) return 0;
     switch (prec) {
     case PREC_F64:
         hipLaunchKernelGGL(step_kernel<double>, grid, block, 0, stream, d_cases, d_work, nwork, parity, export_macros);
@@ -679,6 +778,19 @@ int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int
         break;
     }
     return int(hipGetLastError());
+}
+
+// Resident 256-thread blocks of the step kernel per CU for a precision.
+int step_blocks_per_cu(int prec)
+{
+    int n = 0;
+    hipError_t e;
+    switch (prec) {
+    case PREC_F64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<double>, WAVE * WAVES_PER_BLOCK, 0); break;
+    case PREC_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float>, WAVE * WAVES_PER_BLOCK, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<__half>, WAVE * WAVES_PER_BLOCK, 0); break;
+    }
+    return e == hipSuccess ? n : 0;
 }
 
 int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
