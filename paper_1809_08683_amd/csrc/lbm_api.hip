@@ -31,7 +31,6 @@ constexpr double kCs2 = 1.0 / 3.0;
 // model constants of Sec. 4 used on the host side (rest state, kappa)
 constexpr double kVarpi = 1.0 / 6.0, kGamma1 = -2.0, kGamma2 = 2.0;
 constexpr double kKappa = 2.0 / 3.0 + kGamma1 / 2.0 + kGamma2 / 3.0;
-constexpr int kAlignElems = 32;      // stored rows start on 32-element boundaries
 constexpr int kRedBlocks = 240;
 
 size_t elem_size(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
@@ -46,10 +45,12 @@ struct Layout {
 Layout layout_of(int nx, int ny, int prec)
 {
     Layout L;
-    L.pitch = int(round_up(size_t(nx) + 2, kAlignElems));
+    // enough 64-slot strip regions for the off-wall columns of either kind of
+    // x boundary (periodic needs ceil(nx / 60), walled ceil((nx - 2) / 60))
+    L.pitch = ((nx + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS) * lbm::REGION_SLOTS;
     L.plane = (long long)(ny + 2) * L.pitch;
     const size_t es = elem_size(prec);
-    L.buf_bytes = round_up((size_t(18) * L.plane + kAlignElems) * es, 256);
+    L.buf_bytes = round_up(size_t(18) * L.plane * es, 256);
     L.macro_bytes = round_up(size_t(5) * nx * ny * sizeof(double), 256);
     L.flag_bytes = 256;
     L.total = 2 * L.buf_bytes + L.macro_bytes + L.flag_bytes;
@@ -176,6 +177,7 @@ lbm_status validate(lbm_ctx* c, int nx, int ny, const lbm_eos* eos, double Pr, d
     if (!eos || !relax || !bc || !opt) return fail(c, LBM_EINVAL, "null parameter block");
     if (nx < 1 || ny < 1) return fail(c, LBM_EINVAL, "grid size must be positive");
     if ((long long)nx * ny > (1LL << 31) - 1) return fail(c, LBM_EINVAL, "grid too large");
+    if (nx > (1 << 23)) return fail(c, LBM_EINVAL, "grid too wide (a stored row block must stay below 2 GiB)");
     if (bc->side[0].wall != bc->side[1].wall || bc->side[2].wall != bc->side[3].wall)
         return fail(c, LBM_EINVAL, "opposite sides must both be walls or both periodic");
     if ((bc->side[0].wall && nx < 5) || (bc->side[2].wall && ny < 5))
@@ -213,19 +215,20 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
     P.nx = nx;
     P.ny = ny;
     P.pitch = L.pitch;
-    P.plane = L.plane;
+    P.rowblk = 18LL * L.pitch;
     P.wall_x = bc.side[0].wall ? 1 : 0;
     P.wall_y = bc.side[2].wall ? 1 : 0;
+    P.xlo = P.wall_x;
+    P.nstrips = (nx - 2 * P.wall_x + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS;
     P.eos = e.kind;
     P.visc_law = r.law;
     P.per_mass = o.per_mass ? 1 : 0;
     P.cubic = o.cubic;
     P.extrap_order = bc.extrap_order;
     for (int s = 0; s < 4; ++s) P.side_adiabatic[s] = bc.side[s].adiabatic ? 1 : 0;
-    const size_t es = elem_size(o.prec);
-    // shift so that the first node of every stored row (column 1) is aligned
-    P.buf[0] = base + (kAlignElems - 1) * es;
-    P.buf[1] = base + L.buf_bytes + (kAlignElems - 1) * es;
+    // every stored row, and so every 64-slot strip region, starts 256-byte aligned
+    P.buf[0] = base;
+    P.buf[1] = base + L.buf_bytes;
     P.macro = reinterpret_cast<double*>(base + 2 * L.buf_bytes);
     P.flag = reinterpret_cast<int*>(base + 2 * L.buf_bytes + L.macro_bytes);
 
@@ -238,7 +241,7 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
 }
 
 // Work decomposition of one step.  Wall nodes go 64 per wavefront.  The
-// off-wall region of every case is cut into strips of 62 columns and each
+// off-wall region of every case is cut into strips of 60 columns and each
 // strip into segments of nearly equal height; by default the number of
 // segments is chosen so that all items of a step are resident at once
 // (one round of wavefronts, no tail).  Slots are then laid out so that
@@ -256,14 +259,14 @@ void build_work(lbm_ctx* c, int seg_rows, long long capacity)
         if (P.wall_x) nw += 2 * (P.wall_y ? P.ny - 2 : P.ny);
         for (int b = 0; b < nw; b += 64) wall.push_back({k, 1, b, 0, std::min(64, nw - b), 0});
         const int xr = P.wall_x ? P.nx - 2 : P.nx, yr = P.wall_y ? P.ny - 2 : P.ny;
-        total_cells += (long long)((xr + 61) / 62) * yr;
+        total_cells += (long long)((xr + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS) * yr;
     }
     const long long budget = std::max<long long>(capacity - (long long)wall.size(), 1);
     for (int k = 0; k < nc; ++k) {
         const auto& P = c->P[k];
         const int xlo = P.wall_x, xhi = P.wall_x ? P.nx - 1 : P.nx;
         const int ylo = P.wall_y, yhi = P.wall_y ? P.ny - 1 : P.ny;
-        const int rows = yhi - ylo, strips = (xhi - xlo + 61) / 62;
+        const int rows = yhi - ylo, strips = (xhi - xlo + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS;
         int nseg;
         if (seg_rows > 0) {
             nseg = (rows + seg_rows - 1) / seg_rows;
@@ -277,7 +280,7 @@ void build_work(lbm_ctx* c, int seg_rows, long long capacity)
             const int y0 = ylo + int((long long)rows * g / nseg);
             const int y1 = ylo + int((long long)rows * (g + 1) / nseg);
             if (y1 <= y0) continue;
-            for (int st = 0; st < strips; ++st) inner.push_back({k, 0, xlo + 62 * st, y0, y1 - y0, 0});
+            for (int st = 0; st < strips; ++st) inner.push_back({k, 0, xlo + lbm::STRIP_COLS * st, y0, y1 - y0, 0});
         }
     }
     // bands: XCD-major slots, wall items spread over the bands first

@@ -554,42 +554,76 @@ __device__ __forceinline__ void nonequilibrium(const NodeState<C>& s, const Rate
 // storage codecs of the DF deviations: FP64, FP32, FP16 (FP32 arithmetic)
 // ---------------------------------------------------------------------------
 template <typename S> struct Store;
-#ifndef LBM_NT_STORE
-#define LBM_NT_STORE 0
-#endif
-#ifndef LBM_NT_LOAD
-#define LBM_NT_LOAD 0
-#endif
-template <typename T> __device__ __forceinline__ T ld(const T* p)
+
+// Buffer resources for the streaming rows: a raw (stride 0) resource over
+// one stored row block.  Accesses whose offset lies beyond the record count
+// return zero (loads) or are dropped (stores) by the hardware range check,
+// which the interior march uses to switch off the stores of its halo lanes
+// without a branch.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit data format, gfx9 CDNA
+constexpr int kDropOffset = int(0x80000000u);
+
+// A pointer known to be the same in every lane, moved to scalar registers.
+template <typename T> __device__ __forceinline__ T* uniform_ptr(T* p)
 {
-    if constexpr (LBM_NT_LOAD) return __builtin_nontemporal_load(p);
-    else return *p;
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(v));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(v >> 32));
+    return reinterpret_cast<T*>((static_cast<unsigned long long>(hi) << 32) | lo);
 }
-template <typename T> __device__ __forceinline__ void st(T* p, T v)
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes)
 {
-    if constexpr (LBM_NT_STORE) __builtin_nontemporal_store(v, p);
-    else *p = v;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, int(bytes), kRsrcWord3);
 }
+
 template <> struct Store<double> {
     using C = double;
-    static __device__ __forceinline__ double load(const double* p) { return ld(p); }
-    static __device__ __forceinline__ void store(double* p, double v) { st(p, v); }
+    static __device__ __forceinline__ double load(const double* p) { return *p; }
+    static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
+    static __device__ __forceinline__ double bload(rsrc_t r, int vo, int so)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void bstore(rsrc_t r, int vo, int so, double v)
+    {
+        using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, 0);
+    }
 };
 template <> struct Store<float> {
     using C = float;
-    static __device__ __forceinline__ float load(const float* p) { return ld(p); }
-    static __device__ __forceinline__ void store(float* p, float v) { st(p, v); }
+    static __device__ __forceinline__ float load(const float* p) { return *p; }
+    static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
+    static __device__ __forceinline__ float bload(rsrc_t r, int vo, int so)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void bstore(rsrc_t r, int vo, int so, float v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+    }
 };
 template <> struct Store<__half> {
     using C = float;
     static __device__ __forceinline__ float load(const __half* p)
     {
-        const unsigned short b = ld(reinterpret_cast<const unsigned short*>(p));
+        const unsigned short b = *reinterpret_cast<const unsigned short*>(p);
         return __half2float(__ushort_as_half(b));
     }
     static __device__ __forceinline__ void store(__half* p, float v)
     {
-        st(reinterpret_cast<unsigned short*>(p), __half_as_ushort(__float2half_rn(v)));
+        *reinterpret_cast<unsigned short*>(p) = __half_as_ushort(__float2half_rn(v));
+    }
+    static __device__ __forceinline__ float bload(rsrc_t r, int vo, int so)
+    {
+        const unsigned short b = __builtin_bit_cast(unsigned short, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
+        return __half2float(__ushort_as_half(b));
+    }
+    static __device__ __forceinline__ void bstore(rsrc_t r, int vo, int so, float v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, vo, so, 0);
     }
 };
 

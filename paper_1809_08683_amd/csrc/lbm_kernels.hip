@@ -1,13 +1,19 @@
 // Kernels of the coupled D2Q9 MRT step (Huang, Wu & Adams, arXiv:1809.08683)
 // for gfx950.
 //
-// Storage: two ping-pong buffers of 18 SoA planes (f_0..f_8, g_0..g_8), each
-// plane (ny + 2) rows of `pitch` elements; node (x, y) sits at row y + 1,
-// column x + 1.  The extra frame holds ghost cells on walled sides: a wall
-// node writes every post-collision DF that would leave the domain into the
-// ghost cell it would reach, in the plane of the opposite direction, so the
-// next step's pull reads the bounce-back temporaries of eqs. BB.f and BB.g
-// without any special case.  Periodic sides wrap in the index arithmetic.
+// Storage: two ping-pong buffers of (ny + 2) stored row blocks; a row block
+// holds 18 rows of `pitch` elements, one per DF (f_0..f_8, g_0..g_8), so DF q
+// of node (x, y) sits at element ((y + 1) * 18 + q) * pitch + slot(x).  Along
+// a DF row the columns are kept in 64-slot strip regions (see CaseParams):
+// each interior wavefront stores whole, aligned regions, i.e. whole cache
+// lines, and the two columns next to a strip are kept as copies inside its
+// region, so that only the edge lanes read a neighbouring region.  The extra
+// stored rows, and slots 0-1 of the first region and the two slots after the
+// last column on walled sides, hold ghost cells: a wall node writes every
+// post-collision DF that would leave the domain into the ghost cell it would
+// reach, in the row of the opposite direction, so the next step's pull reads
+// the bounce-back temporaries of eqs. BB.f and BB.g without any special case.
+// Periodic sides wrap in the index arithmetic.
 //
 // One step is one launch.  Each wavefront takes one work item:
 //   - interior item: 64 lanes span 62 output columns plus one halo column
@@ -26,8 +32,8 @@
 namespace lbm {
 
 constexpr int WAVE = 64;
-constexpr int STRIP = WAVE - 2;
 constexpr int WAVES_PER_BLOCK = 4;
+static_assert(REGION_SLOTS == WAVE && STRIP_COLS == WAVE - 4, "one wavefront per strip region");
 
 #define EXq(q) ((q) == 1 || (q) == 5 || (q) == 8 ? 1 : ((q) == 3 || (q) == 6 || (q) == 7 ? -1 : 0))
 #define EYq(q) ((q) == 2 || (q) == 5 || (q) == 6 ? 1 : ((q) == 4 || (q) == 7 || (q) == 8 ? -1 : 0))
@@ -40,9 +46,58 @@ __device__ __forceinline__ int wrap_axis(int v, int n, int walled)
     return v < 0 ? v + n : v;
 }
 
-__device__ __forceinline__ long long node_index(const CaseParams& P, int x, int y)
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// storage slot of column x in [-1, nx] (wrapped on a periodic axis) within a
+// stored DF row: the slot of its owning strip, or for the wall and ghost
+// columns the slots next to the first / last strip's columns
+__device__ __forceinline__ int col_slot(const CaseParams& P, int x)
 {
-    return (long long)(wrap_axis(y, P.ny, P.wall_y) + 1) * P.pitch + (wrap_axis(x, P.nx, P.wall_x) + 1);
+    x = wrap_axis(x, P.nx, P.wall_x);
+    const int r = min(max(floor_div(x - P.xlo, STRIP_COLS), 0), P.nstrips - 1);
+    return r * REGION_SLOTS + (x - P.xlo - r * STRIP_COLS) + 2;
+}
+
+// Calls fn(slot) for every slot that holds column x: its own slot and the
+// copies kept in neighbouring strip regions (slot 1 of the next strip, slot 62
+// of the previous one, and on a periodic axis every region slot 1..62 whose
+// column wraps onto x).
+template <typename F>
+__device__ __forceinline__ void for_each_slot(const CaseParams& P, int x, F&& fn)
+{
+    x = wrap_axis(x, P.nx, P.wall_x);
+    const int own = col_slot(P, x);
+    fn(own);
+    if (P.wall_x) {
+        if (x < P.xlo || x >= P.nx - 1) return;            // wall and ghost columns have no copies
+        const int r = (x - P.xlo) / STRIP_COLS, t = (x - P.xlo) % STRIP_COLS;
+        if (t == 0 && r >= 1) fn((r - 1) * REGION_SLOTS + STRIP_COLS + 2);
+        if (t == STRIP_COLS - 1 && r + 1 < P.nstrips) fn((r + 1) * REGION_SLOTS + 1);
+        return;
+    }
+    const int span_end = (P.nstrips - 1) * STRIP_COLS + STRIP_COLS;   // last column any region slot 62 holds
+    for (int d = x - P.nx; d <= span_end; d += P.nx) {
+        const int r0 = floor_div(d, STRIP_COLS);
+        for (int r = r0 - 1; r <= r0 + 1; ++r) {
+            if (r < 0 || r >= P.nstrips) continue;
+            const int j = d - r * STRIP_COLS + 2;
+            if (j < 1 || j > REGION_SLOTS - 2) continue;
+            const int slot = r * REGION_SLOTS + j;
+            if (slot != own) fn(slot);
+        }
+    }
+}
+
+// element index of stored row block y (row y + 1) and DF q
+__device__ __forceinline__ long long row_index(const CaseParams& P, int q, int y)
+{
+    return ((long long)(wrap_axis(y, P.ny, P.wall_y) + 1) * 18 + q) * P.pitch;
+}
+
+// element index of DF q (0..17) of node (x, y), x in [-1, nx], y in [-1, ny]
+__device__ __forceinline__ long long df_index(const CaseParams& P, int q, int x, int y)
+{
+    return row_index(P, q, y) + col_slot(P, x);
 }
 
 // side indices of a node: x-side (0/1) or -1, y-side (2/3) or -1
@@ -80,23 +135,25 @@ __device__ __forceinline__ void pull_node(const CaseParams& P, const S* src, int
     C f[9], g[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        const long long idx = node_index(P, x - EXq(q), y - EYq(q));
-        f[q] = Store<S>::load(src + q * P.plane + idx);
-        g[q] = Store<S>::load(src + (9 + q) * P.plane + idx);
+        f[q] = Store<S>::load(src + df_index(P, q, x - EXq(q), y - EYq(q)));
+        g[q] = Store<S>::load(src + df_index(P, 9 + q, x - EXq(q), y - EYq(q)));
     }
     to_moments<C>(f, m);
     to_moments<C>(g, n);
 }
 
+// store the 18 DFs of node (x, y) into every slot that holds its column
 template <typename S>
-__device__ __forceinline__ void store_node(const CaseParams& P, S* dst, long long idx,
+__device__ __forceinline__ void store_node(const CaseParams& P, S* dst, int x, int y,
                                            const typename Store<S>::C fb[9], const typename Store<S>::C gb[9])
 {
+    for_each_slot(P, x, [&](int slot) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        Store<S>::store(dst + q * P.plane + idx, fb[q]);
-        Store<S>::store(dst + (9 + q) * P.plane + idx, gb[q]);
-    }
+        for (int q = 0; q < 9; ++q) {
+            Store<S>::store(dst + row_index(P, q, y) + slot, fb[q]);
+            Store<S>::store(dst + row_index(P, 9 + q, y) + slot, gb[q]);
+        }
+    });
 }
 
 // Write the post-collision DFs of a wall node that leave the domain into the
@@ -110,9 +167,10 @@ __device__ __forceinline__ void store_ghosts(const CaseParams& P, S* dst, int x,
         const int tx = x + EXq(q), ty = y + EYq(q);
         const bool out = (P.wall_x && (tx < 0 || tx >= P.nx)) || (P.wall_y && (ty < 0 || ty >= P.ny));
         if (out) {
-            const long long idx = node_index(P, tx, ty);
-            Store<S>::store(dst + OPPq(q) * P.plane + idx, fb[q]);
-            Store<S>::store(dst + (9 + OPPq(q)) * P.plane + idx, gb[q]);
+            for_each_slot(P, tx, [&](int slot) {
+                Store<S>::store(dst + row_index(P, OPPq(q), ty) + slot, fb[q]);
+                Store<S>::store(dst + row_index(P, 9 + OPPq(q), ty) + slot, gb[q]);
+            });
         }
     }
 }
@@ -211,6 +269,23 @@ __device__ __forceinline__ void collide_interior(const CaseParams& P, const Coef
 // ---------------------------------------------------------------------------
 // interior item: march up a strip segment
 // ---------------------------------------------------------------------------
+// Wave priority from progress: a wavefront that has done less of its rows
+// is issued first, so the waves of a CU advance together and finish close to
+// each other instead of leaving a few young waves to run alone at the end.
+#ifndef LBM_FAIR
+#define LBM_FAIR 1
+#endif
+__device__ __forceinline__ void progress_priority(int done, int total)
+{
+    if constexpr (LBM_FAIR) {
+        const int q = (4 * done) / total;      // 0..3 for done < total
+        if (q == 0) __builtin_amdgcn_s_setprio(3);
+        else if (q == 1) __builtin_amdgcn_s_setprio(2);
+        else if (q == 2) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+    }
+}
+
 template <typename C>
 __device__ __forceinline__ C from_left(C v) { return __shfl_up(v, 1, WAVE); }
 template <typename C>
@@ -219,50 +294,78 @@ __device__ __forceinline__ C from_right(C v) { return __shfl_down(v, 1, WAVE); }
 // stored row (0 .. ny+1) of lattice row v in [-1, ny], wrapped on a periodic axis
 __device__ __forceinline__ int stored_row(int v, int n, int walled)
 {
-    if (!walled) v = v < 0 ? v + n : (v >= n ? v - n : v);
+    if (!walled) {
+        v %= n;
+        if (v < 0) v += n;
+    }
     return v + 1;
 }
 
-// Pull the 18 DF deviations of one lattice row into registers.  rb[k]
-// points at stored row (y - 1 + k) of plane 0; col[k] is the stored column
-// of x - 1 + k.  A DF moving along e comes from (x - e_x, y - e_y).
-template <typename S>
-__device__ __forceinline__ void pull_row_raw(gconst<S>* const rb[3], const int col[3], int plane,
-                                             typename Store<S>::C f[9], typename Store<S>::C g[9])
+// interior item: the 64 lanes take the 64 slots of one strip region, i.e.
+// columns X - 2 .. X + 61 of a strip whose own columns are X .. X + 59, and
+// march up the rows [y0, y0 + len).  Lanes 1..62 collide valid nodes (their
+// x-neighbours are lanes 0..63); lanes 2..61 are the strip's own nodes and
+// lanes 1 and 62 refresh the copies of the neighbouring strips' edge columns,
+// so every store covers whole aligned cache lines.  All memory traffic goes
+// through buffer resources: one per stored row block, per-lane byte offsets
+// of the source slots in VGPRs, the DF row inside the block as a scalar
+// offset.  The loop body has no divergent branch: lanes whose slot must not
+// be written get an offset past the record count, which the hardware drops,
+// so the loads of row y + 2 stay in flight across the collision and the
+// stores of row y.
+template <typename S, bool EXPORT>
+__device__ __forceinline__ void interior_item(const CaseParams& P, const WorkItem w, const S* __restrict__ src_in,
+                                              S* __restrict__ dst_in)
 {
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        gconst<S>* base = rb[1 - EYq(q)] + q * plane;
-        const int c = col[1 - EXq(q)];
-        f[q] = Store<S>::load((const S*)(base + c));
-        g[q] = Store<S>::load((const S*)(base + 9 * plane + c));
-    }
-}
-
-template <typename S>
-__device__ void interior_item(const CaseParams& P, const WorkItem& w, gconst<S>* __restrict__ src,
-                              gmut<S>* __restrict__ dst, int export_macros)
-{
+    const S* __restrict__ src = uniform_ptr(src_in);
+    S* __restrict__ dst = uniform_ptr(dst_in);
     using C = typename Store<S>::C;
+    constexpr int ES = int(sizeof(S));
     const Coef<C>& K = coef<C>(P);
     const int lane = threadIdx.x & (WAVE - 1);
-    const int nx = P.nx, ny = P.ny, pitch = P.pitch, plane = int(P.plane);
+    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     const int wall_x = P.wall_x, wall_y = P.wall_y;
-    const int xhi = wall_x ? nx - 1 : nx;
-    const int x = w.x0 - 1 + lane;
-    const bool out_lane = lane >= 1 && lane <= STRIP && x < xhi;
-    const int xc = min(x, xhi);                    // lanes past the halo mirror a valid node
-    const int sx = side_x(P, wrap_axis(xc, nx, wall_x));
-    int col[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) col[k] = wrap_axis(xc - 1 + k, nx, wall_x) + 1;
+    const int xhi = wall_x ? nx - 1 : nx;          // end of the off-wall columns
+    const int X = w.x0;                            // first own column
+    const int region = (X - P.xlo) / STRIP_COLS * REGION_SLOTS;
+    const int c = X - 2 + lane;                    // column of this lane's slot
+    // the node this lane collides: its column, held inside [0, nx) on a walled axis
+    const int cn = wall_x ? min(max(c, 0), nx - 1) : wrap_axis(c, nx, 0);
+    const bool regular = c == cn || !wall_x;
+    const int sx = side_x(P, cn);
+    // byte offset of the slot a pull along e_x reads: inside the own region
+    // for source columns X - 1 .. X + 60 (own columns and the two copies, or
+    // the wall and ghost slots on a walled side), the owning slot otherwise
+    auto src_off = [&](int ex) {
+        const int d = c - ex, p = d - (X - 2);
+        const bool inside = regular && p >= 1 && p <= REGION_SLOTS - 2 && (!wall_x || (d >= -1 && d <= nx));
+        return (inside ? region + p : col_slot(P, cn - ex)) * ES;
+    };
+    const int vo0 = src_off(1), vo1 = src_off(0), vo2 = src_off(-1);
+    // slots this lane stores: all but the wall and ghost slots of a walled side
+    const bool keep = wall_x && (c == -1 || c == 0 || c == nx - 1 || c == nx);
+    const int vo_out = keep ? kDropOffset : (region + lane) * ES;
+    const bool out_lane = lane >= 2 && lane < 2 + STRIP_COLS && c < xhi;   // own nodes
+    const int row_bytes = pitch * ES;
+    const unsigned blk_bytes = unsigned(18 * row_bytes);
+    const long long blk = 18LL * pitch;
+    const int ylast = w.y0 + w.len - 1;
 
-    auto row_ptrs = [&](int yy, gconst<S>* rb[3]) {
+    // pull lattice row yy: DF q comes from (x - e_qx, yy - e_qy)
+    auto pull = [&](int yy, C f[9], C g[9]) {
+        const rsrc_t r_s = make_rsrc(src + stored_row(yy - 1, ny, wall_y) * blk, blk_bytes);
+        const rsrc_t r_c = make_rsrc(src + stored_row(yy, ny, wall_y) * blk, blk_bytes);
+        const rsrc_t r_n = make_rsrc(src + stored_row(yy + 1, ny, wall_y) * blk, blk_bytes);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) rb[k] = src + stored_row(yy - 1 + k, ny, wall_y) * pitch;
+        for (int q = 0; q < 9; ++q) {
+            const rsrc_t r = EYq(q) == 1 ? r_s : (EYq(q) == 0 ? r_c : r_n);
+            const int v = EXq(q) == 1 ? vo0 : (EXq(q) == 0 ? vo1 : vo2);
+            f[q] = Store<S>::bload(r, v, q * row_bytes);
+            g[q] = Store<S>::bload(r, v, (9 + q) * row_bytes);
+        }
     };
     // moments and state of a pulled row
-    auto row_state = [&](int yy, const C f[9], const C g[9], C dm[9], C dn[9], NodeState<C>& st) -> double {
+    auto row_state = [&](int yy, const C f[9], const C g[9], C dm[9], C dn[9], NodeState<C>& st) {
         to_moments<C>(f, dm);
         to_moments<C>(g, dn);
         const int yw = stored_row(yy, ny, wall_y) - 1;
@@ -274,32 +377,25 @@ __device__ void interior_item(const CaseParams& P, const WorkItem& w, gconst<S>*
     C rho_m, p_m;
     const int y0 = w.y0;
     {
-        gconst<S>* rb[3];
         C f[9], g[9], dm[9], dn[9];
         NodeState<C> st;
-        row_ptrs(y0 - 1, rb);
-        pull_row_raw<S>(rb, col, plane, f, g);
+        pull(y0 - 1, f, g);
         row_state(y0 - 1, f, g, dm, dn, st);
         rho_m = st.drho;
         p_m = st.dp;
-        row_ptrs(y0, rb);
-        pull_row_raw<S>(rb, col, plane, f, g);
+        pull(y0, f, g);
         row_state(y0, f, g, m_c, n_c, s_c);
-        row_ptrs(y0 + 1, rb);
-        pull_row_raw<S>(rb, col, plane, f, g);
+        pull(y0 + 1, f, g);
         row_state(y0 + 1, f, g, m_n, n_n, s_n);
     }
 
-    for (int i = 0; i < w.len; ++i) {
-        const int y = y0 + i;
-        const bool more = i + 1 < w.len;
-        // issue the loads of row y + 2 before the collision of row y
+    for (int y = y0; y <= ylast; ++y) {
+        progress_priority(y - y0, w.len);
+        // loads of row y + 2 (on the last row a repeat of row y + 1, which
+        // is in cache and whose state is not used) before the collision
+        const int ynext = y < ylast ? y + 2 : y + 1;
         C fr[9], gr[9];
-        if (more) {
-            gconst<S>* rb[3];
-            row_ptrs(y + 2, rb);
-            pull_row_raw<S>(rb, col, plane, fr, gr);
-        }
+        pull(ynext, fr, gr);
 
         // isotropic gradients d_a phi = 3 sum_q w_q e_qa phi(x + e_q), taken on
         // the deviations rho - rho0 and p - p0
@@ -314,17 +410,15 @@ __device__ void interior_item(const CaseParams& P, const WorkItem& w, gconst<S>*
         const C gp_x = (pE - pW) * C(1.0 / 3.0) + (pNE + pSE - pNW - pSW) * C(1.0 / 12.0);
         const C gp_y = (s_n.dp - p_m) * C(1.0 / 3.0) + (pNE + pNW - pSE - pSW) * C(1.0 / 12.0);
 
-        if (out_lane) {
-            C fb[9], gb[9];
-            collide_interior<C>(P, K, s_c, m_c, n_c, gr_x, gr_y, gp_x, gp_y, fb, gb);
-            gmut<S>* o = dst + (y + 1) * pitch + (x + 1);
+        C fb[9], gb[9];
+        collide_interior<C>(P, K, s_c, m_c, n_c, gr_x, gr_y, gp_x, gp_y, fb, gb);
+        const rsrc_t ro = make_rsrc(dst + (long long)(y + 1) * blk, blk_bytes);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                Store<S>::store((S*)(o + q * plane), fb[q]);
-                Store<S>::store((S*)(o + (9 + q) * plane), gb[q]);
-            }
-            if (export_macros) export_node<C>(P, x, y, s_c, K.T0_d + double(s_c.dT));
+        for (int q = 0; q < 9; ++q) {
+            Store<S>::bstore(ro, vo_out, q * row_bytes, fb[q]);
+            Store<S>::bstore(ro, vo_out, (9 + q) * row_bytes, gb[q]);
         }
+        if (EXPORT && out_lane) export_node<C>(P, c, y, s_c, K.T0_d + double(s_c.dT));
         rho_m = s_c.drho;
         p_m = s_c.dp;
         s_c = s_n;
@@ -333,7 +427,7 @@ __device__ void interior_item(const CaseParams& P, const WorkItem& w, gconst<S>*
             m_c[q] = m_n[q];
             n_c[q] = n_n[q];
         }
-        if (more) row_state(y + 2, fr, gr, m_n, n_n, s_n);
+        row_state(ynext, fr, gr, m_n, n_n, s_n);
     }
 }
 
@@ -438,9 +532,9 @@ __device__ __forceinline__ void tilde_at(const CaseParams& P, const S* src, int 
     Zn[6] -= C(0.5) * y5;
 }
 
-template <typename S>
-__device__ void wall_item(const CaseParams& P, const WorkItem& w, const S* __restrict__ src,
-                          S* __restrict__ dst, int export_macros)
+template <typename S, bool EXPORT>
+__device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w, const S* __restrict__ src,
+                          S* __restrict__ dst)
 {
     using C = typename Store<S>::C;
     const Coef<C>& K = coef<C>(P);
@@ -506,10 +600,9 @@ __device__ void wall_item(const CaseParams& P, const WorkItem& w, const S* __res
     post_collision<C>(s, r, P.cubic, meq, Fm, N, Zm, neq, Qm, Hm, Ht, gr_x, gr_y, gp_x, gp_y, mb, nb);
     from_moments<C>(mb, fb);
     from_moments<C>(nb, gb);
-    const long long idx = (long long)(yb + 1) * P.pitch + (xb + 1);
-    store_node<S>(P, dst, idx, fb, gb);
+    store_node<S>(P, dst, xb, yb, fb, gb);
     store_ghosts<S>(P, dst, xb, yb, fb, gb);
-    if (export_macros) export_node<C>(P, xb, yb, s, T_d);
+    if (EXPORT) export_node<C>(P, xb, yb, s, T_d);
 }
 
 // ---------------------------------------------------------------------------
@@ -520,24 +613,41 @@ __device__ void wall_item(const CaseParams& P, const WorkItem& w, const S* __res
 // ---------------------------------------------------------------------------
 // Register budget per precision: FP32/FP16 storage fit 4 wavefronts per
 // SIMD (<= 128 VGPRs), FP64 fits 2.
-template <typename S> struct Occupancy { static constexpr int waves = 4; };
-template <> struct Occupancy<double> { static constexpr int waves = 2; };
+#ifndef LBM_WAVES_F32
+#define LBM_WAVES_F32 4
+#endif
+#ifndef LBM_WAVES_F64
+#define LBM_WAVES_F64 2
+#endif
+template <typename S> struct Occupancy { static constexpr int waves = LBM_WAVES_F32; };
+template <> struct Occupancy<double> { static constexpr int waves = LBM_WAVES_F64; };
 
-template <typename S>
+// EXPORT: also write the macros of the new time level and the divergence
+// flag (the last step of a call).
+template <typename S, bool EXPORT>
 __global__ __launch_bounds__(WAVE * WAVES_PER_BLOCK)
 __attribute__((amdgpu_waves_per_eu(Occupancy<S>::waves, 8))) void step_kernel(
-    const CaseParams* __restrict__ cases, const WorkItem* __restrict__ work, int nwork, int parity,
-    int export_macros)
+    const CaseParams* __restrict__ cases, const WorkItem* __restrict__ work, int nwork, int parity)
 {
     const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6));
     if (wid >= nwork) return;
-    const WorkItem w = work[wid];
+    // the case table and the work list are read-only during a step: reading
+    // them through the constant address space keeps them in scalar loads and
+    // registers, independent of the vector memory traffic of the DFs
+    const __attribute__((address_space(4))) WorkItem* wk = (const __attribute__((address_space(4))) WorkItem*)work + wid;
+    WorkItem w;
+    w.case_id = wk->case_id;
+    w.kind = wk->kind;
+    w.x0 = wk->x0;
+    w.y0 = wk->y0;
+    w.len = wk->len;
+    w.pad = 0;
     if (w.kind == 2) return;
-    const CaseParams& P = cases[w.case_id];
+    const CaseParams& P = *(const CaseParams*)(((const __attribute__((address_space(4))) CaseParams*)cases) + w.case_id);
     if (w.kind == 0)
-        interior_item<S>(P, w, as_global<S>(P.buf[parity]), as_global_mut<S>(P.buf[parity ^ 1]), export_macros);
+        interior_item<S, EXPORT>(P, w, static_cast<const S*>(P.buf[parity]), static_cast<S*>(P.buf[parity ^ 1]));
     else
-        wall_item<S>(P, w, static_cast<const S*>(P.buf[parity]), static_cast<S*>(P.buf[parity ^ 1]), export_macros);
+        wall_item<S, EXPORT>(P, w, static_cast<const S*>(P.buf[parity]), static_cast<S*>(P.buf[parity ^ 1]));
 }
 
 // ---------------------------------------------------------------------------
@@ -630,8 +740,7 @@ __global__ __launch_bounds__(256) void init_kernel(const CaseParams* __restrict_
     from_moments<C>(mb, fb);
     from_moments<C>(nb, gb);
     S* dst = static_cast<S*>(P.buf[parity]);
-    const long long idx = (long long)(y + 1) * P.pitch + (x + 1);
-    store_node<S>(P, dst, idx, fb, gb);
+    store_node<S>(P, dst, x, y, fb, gb);
     if (sx >= 0 || sy >= 0) store_ghosts<S>(P, dst, x, y, fb, gb);
     export_node<C>(P, x, y, s, T_d);
 }
@@ -766,15 +875,24 @@ int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int
     const dim3 block(WAVE * WAVES_PER_BLOCK);
     const dim3 grid((nwork + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
     if (nwork == 0) return 0;
-    switch (prec) {
-    case PREC_F64:
-        hipLaunchKernelGGL(step_kernel<double>, grid, block, 0, stream, d_cases, d_work, nwork, parity, export_macros);
+    switch (prec * 2 + (export_macros ? 1 : 0)) {
+    case PREC_F64 * 2:
+        hipLaunchKernelGGL((step_kernel<double, false>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
         break;
-    case PREC_F32:
-        hipLaunchKernelGGL(step_kernel<float>, grid, block, 0, stream, d_cases, d_work, nwork, parity, export_macros);
+    case PREC_F64 * 2 + 1:
+        hipLaunchKernelGGL((step_kernel<double, true>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
+        break;
+    case PREC_F32 * 2:
+        hipLaunchKernelGGL((step_kernel<float, false>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
+        break;
+    case PREC_F32 * 2 + 1:
+        hipLaunchKernelGGL((step_kernel<float, true>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
+        break;
+    case PREC_F16S * 2:
+        hipLaunchKernelGGL((step_kernel<__half, false>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
         break;
     default:
-        hipLaunchKernelGGL(step_kernel<__half>, grid, block, 0, stream, d_cases, d_work, nwork, parity, export_macros);
+        hipLaunchKernelGGL((step_kernel<__half, true>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
         break;
     }
     return int(hipGetLastError());
@@ -786,9 +904,9 @@ int step_blocks_per_cu(int prec)
     int n = 0;
     hipError_t e;
     switch (prec) {
-    case PREC_F64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<double>, WAVE * WAVES_PER_BLOCK, 0); break;
-    case PREC_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float>, WAVE * WAVES_PER_BLOCK, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<__half>, WAVE * WAVES_PER_BLOCK, 0); break;
+    case PREC_F64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<double, false>, WAVE * WAVES_PER_BLOCK, 0); break;
+    case PREC_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, false>, WAVE * WAVES_PER_BLOCK, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<__half, false>, WAVE * WAVES_PER_BLOCK, 0); break;
     }
     return e == hipSuccess ? n : 0;
 }

@@ -27,13 +27,23 @@ struct Coef {
     double R_d, a_d, b_d, bcs_d;           // EOS constants for FP64 evaluation
 };
 
+// Columns are stored strip by strip: strip s owns the off-wall columns
+// [xlo + 60 s, xlo + 60 s + 60) and keeps them, with copies of two neighbour
+// columns, in a region of 64 slots: slot j holds column xlo + 60 s - 2 + j.
+// Slots 2..61 are the strip's own columns, slots 1 and 62 copies of the
+// neighbouring strips' edge columns (the left wall and ghost columns sit in
+// slots 1 and 0 of strip 0, the right ones after the last strip's columns).
+constexpr int STRIP_COLS = 60;
+constexpr int REGION_SLOTS = 64;
+
 struct CaseParams {
-    int nx, ny, pitch;         // pitch: elements per stored row (>= nx + 2)
+    int nx, ny, pitch;         // pitch: elements per stored row of one DF = REGION_SLOTS * strips (or more)
+    int xlo, nstrips;          // first off-wall column, number of strips
     int wall_x, wall_y;        // 1: both sides of that axis are walls
-    long long plane;           // elements per stored plane = (ny + 2) * pitch
+    long long rowblk;          // elements per stored row block = 18 * pitch
     int eos, visc_law, per_mass, cubic, extrap_order;
     int side_adiabatic[4];
-    void* buf[2];              // ping-pong DF buffers (18 planes each, f then g)
+    void* buf[2];              // ping-pong DF buffers: (ny + 2) row blocks of 18 DF rows (f then g)
     double* macro;             // [5][ny][nx]: rho, ux, uy, T, p (written on export steps)
     int* flag;                 // divergence flag of this case
     Coef<double> cd;
@@ -41,7 +51,7 @@ struct CaseParams {
 };
 
 // One wavefront's share of a step.
-//   kind 0: interior strip, output columns [x0, x0 + 62) clipped to the off-wall
+//   kind 0: interior strip, output columns [x0, x0 + 60) clipped to the off-wall
 //           range, rows [y0, y0 + len)
 //   kind 1: wall nodes [x0, x0 + len) of the case's wall-node enumeration
 struct WorkItem {
