@@ -240,26 +240,39 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
 
 }
 
-// Work decomposition of one step.  Wall nodes go 64 per wavefront.  The
-// off-wall region of every case is cut into strips of 60 columns and each
-// strip into segments of nearly equal height; by default the number of
-// segments is chosen so that all items of a step are resident at once
-// (one round of wavefronts, no tail).  Slots are then laid out so that
-// block b runs on XCD b % 8 with a contiguous band of rows, wall items
-// first.
-void build_work(lbm_ctx* c, int seg_rows, long long capacity)
+// Work decomposition of one step.  The off-wall region of every case is cut
+// into strips of 60 columns and each strip into segments of nearly equal
+// height; by default the number of segments is chosen so that all items of
+// a step are resident at once (one round of wavefronts).  Wall nodes are
+// split over at least one wavefront per CU (up to 64 nodes each) and every
+// wall wavefront goes to a block of its own, so that each CU carries the same
+// mix of wall and interior work.  Block b runs on XCD b % 8; the interior
+// items of one contiguous band of rows go to the blocks of one XCD.
+bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu)
 {
+    constexpr int NX = 8;
+    constexpr int PB = 4;   // wavefronts per block
     const int nc = int(c->P.size());
-    std::vector<lbm::WorkItem> wall, inner;
-    long long total_cells = 0;   // strip-rows over all cases
+    const long long nblocks = (long long)round_up(size_t(std::max(cus, 1)) * size_t(std::max(blocks_per_cu, 1)), NX);
+    const long long capacity = nblocks * PB;
+    std::vector<int> nwall(nc, 0);
+    long long total_wall = 0, total_cells = 0;   // wall nodes, strip-rows over all cases
     for (int k = 0; k < nc; ++k) {
         const auto& P = c->P[k];
-        int nw = 0;
-        if (P.wall_y) nw += 2 * P.nx;
-        if (P.wall_x) nw += 2 * (P.wall_y ? P.ny - 2 : P.ny);
-        for (int b = 0; b < nw; b += 64) wall.push_back({k, 1, b, 0, std::min(64, nw - b), 0});
+        if (P.wall_y) nwall[k] += 2 * P.nx;
+        if (P.wall_x) nwall[k] += 2 * (P.wall_y ? P.ny - 2 : P.ny);
+        total_wall += nwall[k];
         const int xr = P.wall_x ? P.nx - 2 : P.nx, yr = P.wall_y ? P.ny - 2 : P.ny;
         total_cells += (long long)((xr + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS) * yr;
+    }
+    std::vector<lbm::WorkItem> wall, inner;
+    if (total_wall > 0) {
+        long long nw = (total_wall + 63) / 64;
+        nw = std::max(nw, std::min<long long>(cus, (total_wall + 15) / 16));
+        nw = std::min(nw, nblocks);
+        const int chunk = int((total_wall + nw - 1) / nw);
+        for (int k = 0; k < nc; ++k)
+            for (int b = 0; b < nwall[k]; b += chunk) wall.push_back({k, 1, b, 0, std::min(chunk, nwall[k] - b), 0});
     }
     const long long budget = std::max<long long>(capacity - (long long)wall.size(), 1);
     for (int k = 0; k < nc; ++k) {
@@ -283,22 +296,42 @@ void build_work(lbm_ctx* c, int seg_rows, long long capacity)
             for (int st = 0; st < strips; ++st) inner.push_back({k, 0, xlo + lbm::STRIP_COLS * st, y0, y1 - y0, 0});
         }
     }
-    // bands: XCD-major slots, wall items spread over the bands first
-    constexpr int NX = 8;
-    std::vector<std::vector<lbm::WorkItem>> band(NX);
-    for (size_t i = 0; i < wall.size(); ++i) band[i % NX].push_back(wall[i]);
-    for (size_t i = 0; i < inner.size(); ++i) band[i * NX / inner.size()].push_back(inner[i]);
-    size_t longest = 0;
-    for (auto& b : band) longest = std::max(longest, b.size());
-    const size_t per_block = 4;
-    const size_t blocks_per_band = (longest + per_block - 1) / per_block;
-    c->work.assign(blocks_per_band * NX * per_block, lbm::WorkItem{0, 2, 0, 0, 0, 0});
-    for (int k = 0; k < NX; ++k)
-        for (size_t j = 0; j < band[k].size(); ++j) {
-            const size_t blk = (j / per_block) * NX + k;
-            c->work[blk * per_block + j % per_block] = band[k][j];
+    // wall item i: slot i / nblocks of block i % nblocks
+    std::vector<int> used(size_t(nblocks), 0);
+    std::vector<std::pair<long long, lbm::WorkItem>> placed;
+    for (size_t i = 0; i < wall.size(); ++i) {
+        long long blk = (long long)i % nblocks;
+        while (blk < (long long)used.size() && used[size_t(blk)] >= PB) ++blk;
+        if (blk == (long long)used.size()) used.push_back(0);
+        placed.push_back({blk * PB + used[size_t(blk)], wall[i]});
+        ++used[size_t(blk)];
+    }
+    const long long wall_blocks = (long long)used.size();
+    // interior band k (a contiguous run of the item list) fills the free
+    // slots of blocks k, k + 8, ... in order; blocks past the resident count
+    // are added if a band needs them
+    long long total_blocks = (long long)round_up(size_t(wall_blocks), NX);
+    for (int k = 0; k < NX; ++k) {
+        const size_t lo = inner.size() * k / NX, hi = inner.size() * (k + 1) / NX;
+        long long blk = k;
+        int fill = blk < wall_blocks ? used[size_t(blk)] : 0;
+        for (size_t i = lo; i < hi; ++i) {
+            while (fill >= PB) {
+                blk += NX;
+                fill = blk < wall_blocks ? used[size_t(blk)] : 0;
+            }
+            placed.push_back({blk * PB + fill, inner[i]});
+            ++fill;
+            total_blocks = std::max(total_blocks, (blk / NX + 1) * NX);
         }
+    }
+    c->work.assign(size_t(total_blocks * PB), lbm::WorkItem{0, 2, 0, 0, 0, 0});
+    for (const auto& pr : placed) {
+        if (pr.first < 0 || pr.first >= (long long)c->work.size() || c->work[size_t(pr.first)].kind != 2) return false;
+        c->work[size_t(pr.first)] = pr.second;
+    }
     c->n_items = (long long)(wall.size() + inner.size());
+    return true;
 }
 
 lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* eos, const double* Pr,
@@ -356,9 +389,8 @@ lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* 
     }
     int cus = 0;
     HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
-    const int bpc = lbm::step_blocks_per_cu(c->prec);
-    const long long capacity = (long long)std::max(cus, 1) * std::max(bpc, 1) * 4;
-    build_work(c, opt[0].seg_rows, capacity);
+    if (!build_work(c, opt[0].seg_rows, cus, lbm::step_blocks_per_cu(c->prec)))
+        return fail(c, LBM_EDEVICE, "internal error: work list slots overlap");
     void* p = nullptr;
     HIP_TRY(c, hipMalloc(&p, sizeof(lbm::CaseParams) * ncases));
     c->allocs.push_back(p);

@@ -643,6 +643,7 @@ __attribute__((amdgpu_waves_per_eu(Occupancy<S>::waves, 8))) void step_kernel(
     w.len = wk->len;
     w.pad = 0;
     if (w.kind == 2) return;
+    progress_priority(0, 1);
     const CaseParams& P = *(const CaseParams*)(((const __attribute__((address_space(4))) CaseParams*)cases) + w.case_id);
     if (w.kind == 0)
         interior_item<S, EXPORT>(P, w, static_cast<const S*>(P.buf[parity]), static_cast<S*>(P.buf[parity ^ 1]));
