@@ -17,6 +17,7 @@ namespace lbm {
 int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
                 int export_macros, hipStream_t stream);
 int step_blocks_per_cu(int prec);
+int step_lockstep(int prec);
 int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
                 int parity, hipStream_t stream);
 int launch_totals(const CaseParams* d_cases, int case_id, double* d_partial, int nblocks, double* d_out,
@@ -244,11 +245,13 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
 // into strips of 60 columns and each strip into segments of nearly equal
 // height; by default the number of segments is chosen so that all items of
 // a step are resident at once (one round of wavefronts).  Wall nodes are
-// split over at least one wavefront per CU (up to 64 nodes each) and every
-// wall wavefront goes to a block of its own, so that each CU carries the same
-// mix of wall and interior work.  Block b runs on XCD b % 8; the interior
-// items of one contiguous band of rows go to the blocks of one XCD.
-bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu)
+// split over at least one wavefront per CU (up to 64 nodes each).  Without
+// lockstep every wall wavefront goes to a block of its own, so that each CU
+// carries the same mix of wall and interior work; with lockstep the wall
+// wavefronts fill blocks of their own.  Block b runs on XCD b % 8; the
+// interior items of one contiguous band of rows go to the blocks of one XCD,
+// four neighbouring strips of a segment per block.
+bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, bool lockstep)
 {
     constexpr int NX = 8;
     constexpr int PB = 4;   // wavefronts per block
@@ -296,16 +299,22 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu)
             for (int st = 0; st < strips; ++st) inner.push_back({k, 0, xlo + lbm::STRIP_COLS * st, y0, y1 - y0, 0});
         }
     }
-    // wall item i: slot i / nblocks of block i % nblocks
+    // Wall item i goes to slot i / nblocks of block i % nblocks (one per block
+    // first, spreading them over the CUs).  When interior waves march in
+    // lockstep, a block must not mix them with wall waves: wall items then
+    // fill whole blocks of their own, spread over the XCDs.
     std::vector<int> used(size_t(nblocks), 0);
     std::vector<std::pair<long long, lbm::WorkItem>> placed;
     for (size_t i = 0; i < wall.size(); ++i) {
-        long long blk = (long long)i % nblocks;
+        long long blk = lockstep ? (long long)(i / PB) : (long long)i % nblocks;
         while (blk < (long long)used.size() && used[size_t(blk)] >= PB) ++blk;
-        if (blk == (long long)used.size()) used.push_back(0);
+        while (blk >= (long long)used.size()) used.push_back(0);
         placed.push_back({blk * PB + used[size_t(blk)], wall[i]});
         ++used[size_t(blk)];
     }
+    if (lockstep)
+        for (auto& u : used)
+            if (u > 0) u = PB;
     const long long wall_blocks = (long long)used.size();
     // interior band k (a contiguous run of the item list) fills the free
     // slots of blocks k, k + 8, ... in order; blocks past the resident count
@@ -389,7 +398,7 @@ lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* 
     }
     int cus = 0;
     HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
-    if (!build_work(c, opt[0].seg_rows, cus, lbm::step_blocks_per_cu(c->prec)))
+    if (!build_work(c, opt[0].seg_rows, cus, lbm::step_blocks_per_cu(c->prec), lbm::step_lockstep(c->prec) != 0))
         return fail(c, LBM_EDEVICE, "internal error: work list slots overlap");
     void* p = nullptr;
     HIP_TRY(c, hipMalloc(&p, sizeof(lbm::CaseParams) * ncases));

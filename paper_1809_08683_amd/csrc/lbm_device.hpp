@@ -233,6 +233,37 @@ __device__ __forceinline__ double state_from_moments(const Coef<C>& K, int eos, 
     return T_d;
 }
 
+// Node of an interior strip whose lane may sit on an x-wall (wl): the
+// off-wall formulas of state_from_moments with, on a wall lane, the wall
+// velocity and (Dirichlet wall, dir) the wall temperature selected in, which
+// gives state_wall's result for the wall lane without a divergent branch.
+template <typename C>
+__device__ __forceinline__ double state_select(const Coef<C>& K, int eos, int per_mass, const C dm[9], C dn0,
+                                               bool wl, C ubx, C uby, bool dir, double Tw, NodeState<C>& s)
+{
+    s.drho = dm[0];
+    const C rho = K.rho0 + s.drho;
+    s.inv_rho = rcp<C>(rho);
+    const C Fx = per_mass ? rho * K.fx : K.fx;
+    const C Fy = per_mass ? rho * K.fy : K.fy;
+    const C jx = dm[3] + C(0.5) * Fx, jy = dm[5] + C(0.5) * Fy;
+    s.jx = wl ? rho * ubx : jx;
+    s.jy = wl ? rho * uby : jy;
+    s.ux = wl ? ubx : jx * s.inv_rho;
+    s.uy = wl ? uby : jy * s.inv_rho;
+    const C drhoE = dn0 + C(0.5) * (s.ux * Fx + s.uy * Fy);
+    const double rho_d = K.rho0_d + double(s.drho);
+    const double uxd = double(s.ux), uyd = double(s.uy);
+    const double u2 = uxd * uxd + uyd * uyd;
+    const double E_a = (K.rhoE0_d + double(drhoE)) * rcp_d(rho_d);
+    const double T_d = dir ? Tw : (E_a - 0.5 * u2) * K.inv_cv_d;
+    const double E_d = dir ? K.cv_d * Tw + 0.5 * u2 : E_a;
+    s.drhoE = dir ? C(rho_d * E_d - K.rhoE0_d) : drhoE;
+    s.dT = C(T_d - K.T0_d);
+    complete_state<C>(K, eos, s, rho_d, T_d, E_d);
+    return T_d;
+}
+
 // Wall node (Sec. 3.1): rho from the bounce-back-completed DFs, u prescribed,
 // T prescribed (Dirichlet) or from rho E = sum g + q_e/2 (adiabatic).
 template <typename C>

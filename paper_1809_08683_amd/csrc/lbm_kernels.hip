@@ -33,6 +33,26 @@ namespace lbm {
 
 constexpr int WAVE = 64;
 constexpr int WAVES_PER_BLOCK = 4;
+
+// Per storage format: the wavefronts per SIMD that the register budget of
+// the step kernel allows; whether the interior waves of a block advance row
+// by row together (a barrier per row, so that the edge lanes of neighbouring
+// strips read the lines their neighbours fetch at the same moment); whether
+// the strips next to an x-wall select the wall state of their wall lanes
+// instead of branching (needs a few more registers).
+template <typename S> struct Tuning;
+template <> struct Tuning<double> {
+    static constexpr int waves = 2;
+    static constexpr bool lockstep = true, edge_select = true;
+};
+template <> struct Tuning<float> {
+    static constexpr int waves = 3;
+    static constexpr bool lockstep = true, edge_select = true;
+};
+template <> struct Tuning<__half> {
+    static constexpr int waves = 4;
+    static constexpr bool lockstep = false, edge_select = false;
+};
 static_assert(REGION_SLOTS == WAVE && STRIP_COLS == WAVE - 4, "one wavefront per strip region");
 
 #define EXq(q) ((q) == 1 || (q) == 5 || (q) == 8 ? 1 : ((q) == 3 || (q) == 6 || (q) == 7 ? -1 : 0))
@@ -364,12 +384,22 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
             g[q] = Store<S>::bload(r, v, (9 + q) * row_bytes);
         }
     };
-    // moments and state of a pulled row
+    // A strip next to an x-wall has lanes on the wall column; their state
+    // takes the wall velocity / temperature by selection (no divergence).
+    const bool edge = Tuning<S>::edge_select && wall_x && (X - 2 <= 0 || X + REGION_SLOTS - 3 >= nx - 1);
+    // moments and state of a pulled row (wall rows: uniform branch to the wall formulas)
     auto row_state = [&](int yy, const C f[9], const C g[9], C dm[9], C dn[9], NodeState<C>& st) {
         to_moments<C>(f, dm);
         to_moments<C>(g, dn);
-        const int yw = stored_row(yy, ny, wall_y) - 1;
-        return node_state<C>(P, K, sx, side_y(P, yw), dm, dn[0], st);
+        const int sy = side_y(P, stored_row(yy, ny, wall_y) - 1);
+        if (sy >= 0 || !Tuning<S>::edge_select) return node_state<C>(P, K, sx, sy, dm, dn[0], st);
+        if (edge) {
+            const bool right = sx == 1;
+            const bool dir = sx >= 0 && !(right ? P.side_adiabatic[1] : P.side_adiabatic[0]);
+            return state_select<C>(K, P.eos, P.per_mass, dm, dn[0], sx >= 0, right ? K.side_ux[1] : K.side_ux[0],
+                                   right ? K.side_uy[1] : K.side_uy[0], dir, right ? K.side_T[1] : K.side_T[0], st);
+        }
+        return state_from_moments<C>(K, P.eos, P.per_mass, dm, dn[0], st);
     };
 
     C m_c[9], n_c[9], m_n[9], n_n[9];
@@ -390,6 +420,7 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     }
 
     for (int y = y0; y <= ylast; ++y) {
+        if constexpr (Tuning<S>::lockstep) __syncthreads();
         progress_priority(y - y0, w.len);
         // loads of row y + 2 (on the last row a repeat of row y + 1, which
         // is in cache and whose state is not used) before the collision
@@ -611,22 +642,12 @@ __device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w,
 // start first and each XCD's blocks cover one contiguous band of rows;
 // kind 2 marks an empty slot.
 // ---------------------------------------------------------------------------
-// Register budget per precision: FP32/FP16 storage fit 4 wavefronts per
-// SIMD (<= 128 VGPRs), FP64 fits 2.
-#ifndef LBM_WAVES_F32
-#define LBM_WAVES_F32 4
-#endif
-#ifndef LBM_WAVES_F64
-#define LBM_WAVES_F64 2
-#endif
-template <typename S> struct Occupancy { static constexpr int waves = LBM_WAVES_F32; };
-template <> struct Occupancy<double> { static constexpr int waves = LBM_WAVES_F64; };
 
 // EXPORT: also write the macros of the new time level and the divergence
 // flag (the last step of a call).
 template <typename S, bool EXPORT>
 __global__ __launch_bounds__(WAVE * WAVES_PER_BLOCK)
-__attribute__((amdgpu_waves_per_eu(Occupancy<S>::waves, 8))) void step_kernel(
+__attribute__((amdgpu_waves_per_eu(Tuning<S>::waves, 8))) void step_kernel(
     const CaseParams* __restrict__ cases, const WorkItem* __restrict__ work, int nwork, int parity)
 {
     const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6));
@@ -897,6 +918,17 @@ int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int
         break;
     }
     return int(hipGetLastError());
+}
+
+// Whether the interior waves of a block march in lockstep (the work list
+// then keeps wall items out of interior blocks).
+int step_lockstep(int prec)
+{
+    switch (prec) {
+    case PREC_F64: return Tuning<double>::lockstep;
+    case PREC_F32: return Tuning<float>::lockstep;
+    default: return Tuning<__half>::lockstep;
+    }
 }
 
 // Resident 256-thread blocks of the step kernel per CU for a precision.
