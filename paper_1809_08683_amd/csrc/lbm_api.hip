@@ -270,10 +270,12 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, bool locks
     }
     std::vector<lbm::WorkItem> wall, inner;
     if (total_wall > 0) {
+        // at most 64 nodes (one per lane) per wavefront, at least one
+        // wavefront per CU while that leaves 16 or more nodes to each
         long long nw = (total_wall + 63) / 64;
         nw = std::max(nw, std::min<long long>(cus, (total_wall + 15) / 16));
-        nw = std::min(nw, nblocks);
         const int chunk = int((total_wall + nw - 1) / nw);
+        if (chunk > 64) return false;
         for (int k = 0; k < nc; ++k)
             for (int b = 0; b < nwall[k]; b += chunk) wall.push_back({k, 1, b, 0, std::min(chunk, nwall[k] - b), 0});
     }
@@ -399,7 +401,7 @@ lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* 
     int cus = 0;
     HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
     if (!build_work(c, opt[0].seg_rows, cus, lbm::step_blocks_per_cu(c->prec), lbm::step_lockstep(c->prec) != 0))
-        return fail(c, LBM_EDEVICE, "internal error: work list slots overlap");
+        return fail(c, LBM_EDEVICE, "internal error: inconsistent work list");
     void* p = nullptr;
     HIP_TRY(c, hipMalloc(&p, sizeof(lbm::CaseParams) * ncases));
     c->allocs.push_back(p);

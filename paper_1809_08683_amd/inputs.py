@@ -142,9 +142,15 @@ def cavity(N=512, Ra=1e6, eps=0.6, Pr=0.71, nu0=0.1, Ma=None, bulk_ratio=None, n
     return c
 
 
-def batch_cases(seed=2, n=64, nu0=0.1, prec="f32") -> list:
+def batch_cases(seed=2, n=64, Ma=0.05, nu_min=0.1, prec="f32") -> list:
     """Uneven cavities: N in {128,256,512,1024}, log10 Ra in U[3,8],
-    eps in U[0.1,0.6], Pr in {0.71,1,7}; four draws per case from one stream."""
+    eps in U[0.1,0.6], Pr in {0.71,1,7}; four draws per case from one stream.
+
+    Each case is set up at buoyancy Mach number Ma (g and mu0 from Ra as in
+    cavity(Ma=...)).  Where that viscosity would fall below nu_min (the
+    scheme's linear stability limit at tau0 = 0.8) the case runs at nu_min
+    with the same g, i.e. at the lower effective Rayleigh number
+    Ra * (nu_Ma / nu_min)^2, recorded as "Ra_eff"."""
     u = uniform01(seed, 4 * n).reshape(n, 4)
     sizes = (128, 256, 512, 1024)
     prs = (0.71, 1.0, 7.0)
@@ -154,7 +160,13 @@ def batch_cases(seed=2, n=64, nu0=0.1, prec="f32") -> list:
         Ra = 10.0 ** (3.0 + 5.0 * u[k, 1])
         eps = 0.1 + 0.5 * u[k, 2]
         Pr = prs[min(int(u[k, 3] * 3), 2)]
-        out.append(cavity(N=N, Ra=Ra, eps=eps, Pr=Pr, nu0=nu0, prec=prec))
+        c = cavity(N=N, Ra=Ra, eps=eps, Pr=Pr, Ma=Ma, prec=prec)
+        c["Ra_eff"] = Ra
+        if c["nu0"] < nu_min:
+            c["Ra_eff"] = Ra * (c["nu0"] / nu_min) ** 2
+            c["nu0"] = nu_min
+            c["Ma_ref"] = math.sqrt(c["Ra_eff"]) * nu_min / (N - 1) / math.sqrt(CS2)
+        out.append(c)
     return out
 
 
