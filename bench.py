@@ -66,6 +66,44 @@ def time_path(case, prec, steps, warmup, seg_rows=0):
     return res
 
 
+def time_batch(steps, warmup, prec="f32"):
+    """The batched sweep: 64 cavities of uneven size (N in {128..1024}) and
+    Rayleigh number, one launch per step for all of them."""
+    import torch
+    from paper_1809_08683_amd import inputs, lbm
+
+    cases = inputs.batch_cases(seed=2, n=64, prec=prec)
+    nodes = sum(c["nx"] * c["ny"] for c in cases)
+    stream = torch.cuda.Stream()
+    b = lbm.Batch(cases, stream=stream)
+    for k, c in enumerate(cases):
+        b.init(k, rho=1.0 + 1e-6 * inputs.noise(3 + k, c["nx"] * c["ny"]).reshape(c["ny"], c["nx"]))
+    if warmup:
+        b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kernel_ms = b.step_timed(steps)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    flags = b.flags()
+    per_step_s = kernel_ms * 1e-3 / steps
+    res = {
+        "workload": "64 cavities, N in {128,256,512,1024} (seed 2), Ra log-uniform in [1e3,1e8], "
+                    "eps in [0.1,0.6], Pr in {0.71,1,7}, buoyancy Mach 0.05 (nu0 >= 0.1)",
+        "prec": prec,
+        "nodes": nodes,
+        "mlups": nodes * steps / wall_s / 1e6,
+        "ms_per_step": wall_s * 1e3 / steps,
+        "kernel_mlups": nodes / per_step_s / 1e6,
+        "achieved_GBs": BYTES_PER_NODE[prec] * nodes / per_step_s / 1e9,
+        "diverged_cases": int(sum(flags)),
+        "work_items": b.work_items,
+    }
+    res["frac_hbm"] = res["achieved_GBs"] / PEAK_HBM_GBS
+    b.close()
+    return res
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 CPU oracle (single thread, as written) on a bounded sample:
     a 256 x 256 cavity (eps 0.6, Ra 1e5) stepped until ~15 s have passed."""
@@ -93,6 +131,7 @@ def main():
     ap.add_argument("--paths", default="f32,f16s,f64")
     ap.add_argument("--seg-rows", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU slab decomposition is "
@@ -113,6 +152,11 @@ def main():
         log(f"bench: {args.n}^2 cavity {prec}: warmup {args.warmup}, timed {args.steps} steps")
         paths[prec] = time_path(case, prec, args.steps, args.warmup, args.seg_rows)
         log(f"bench: {prec}: {json.dumps(paths[prec])}")
+    batch = None
+    if not args.no_batch:
+        log("bench: 64-cavity batch f32: warmup 20, timed 100 steps")
+        batch = time_batch(100, 20)
+        log(f"bench: batch: {json.dumps(batch)}")
     copy_gbs, _ = lbm.copy_bandwidth(1 << 30, iters=20)
     log(f"bench: device copy bandwidth {copy_gbs:.0f} GB/s")
 
@@ -149,6 +193,8 @@ def main():
                   for k, v in paths.items()},
         "copy_bandwidth_GBs": round(copy_gbs, 1),
     }
+    if batch is not None:
+        out["batch"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in batch.items()}
     if "f64" in paths:
         out["speedup_vs_f64"] = {k: round(v["mlups"] / paths["f64"]["mlups"], 3) for k, v in paths.items()}
     if not args.no_cpu:
