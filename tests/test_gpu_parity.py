@@ -266,3 +266,34 @@ def test_invalid_init_rejected():
     bad[3, 4] = -1.0
     with pytest.raises(lbm.LBMError):
         g.init(rho=bad)
+
+
+# ---------------------------------------------------------------- Nusselt
+_NU_CASE = dict(N=256, Ra=1e5, eps=0.6, nu0=0.1, noise_seed=1)
+
+
+def _nu_run(prec, steps):
+    c = inputs.cavity(prec=prec, **_NU_CASE)
+    g = lbm.Context(c).init(**c["init"])
+    g.step(steps)
+    nu = g.nusselt(0)
+    g.close()
+    return nu
+
+
+def test_nusselt_cavity_256_against_table2_and_fp64(golden):
+    """256^2 cavity, Ra = 1e5, eps = 0.6 (Table 1 pairing), 100000 steps:
+    the FP64 path reaches a steady mean hot-wall Nu within 1% of the value
+    Table 2 prints for this Rayleigh number (4.4836), and the FP32 path stays
+    within 0.5% of the FP64 path (whose every step matches the oracle to
+    1e-10 in the parity tests above).  The FP16-offset path is reported: its
+    16-bit density DFs limit it to about 10% here (see the design notes)."""
+    t2 = golden["cavity_table2_present"]
+    ref = t2["Nu_ave"][t2["Ra"].index(1e5)]
+    nu = {p: _nu_run(p, 100000) for p in ("f64", "f32", "f16s")}
+    rel = {p: (nu[p] - nu["f64"]) / nu["f64"] for p in nu}
+    print("Nu", {p: round(v, 5) for p, v in nu.items()}, "rel vs f64", {p: f"{v:.1e}" for p, v in rel.items()},
+          f"f64 vs Table 2: {(nu['f64'] - ref) / ref:.2e}", flush=True)
+    assert abs(nu["f64"] - ref) / ref < 0.01
+    assert abs(rel["f32"]) < 5e-3
+    assert np.isfinite(nu["f16s"]) and abs(rel["f16s"]) < 0.25
