@@ -95,12 +95,15 @@ typedef struct {
     int extrap_order;    /* 1 or 2 (eq. neq.extrapolation) */
 } lbm_boundary;
 
-/* Storage precision of the DFs:
- *   FP64  - FP64 storage and arithmetic;
- *   FP32  - FP32 storage and arithmetic, temperature recovered in FP64;
- *   FP16S - FP16 storage of the offsets from the rest-state equilibrium,
- *           FP32 arithmetic, temperature recovered in FP64. */
-typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 } lbm_precision;
+/* Storage precision of the DFs (always stored as offsets from the
+ * rest-state equilibrium):
+ *   FP64   - FP64 storage and arithmetic;
+ *   FP32   - FP32 storage and arithmetic, temperature recovered in FP64;
+ *   FP16S  - FP16 storage of f and g, FP32 arithmetic, temperature in FP64;
+ *   F32G16 - FP32 storage of the density DFs f, FP16 storage of the
+ *            energy DFs g, FP32 arithmetic, temperature in FP64 (the 16-bit
+ *            density DFs are what limits FP16S accuracy). */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2, LBM_F32G16 = 3 } lbm_precision;
 
 typedef struct {
     double fx, fy;       /* force per unit volume, or per unit mass if per_mass */

@@ -34,7 +34,9 @@ constexpr double kVarpi = 1.0 / 6.0, kGamma1 = -2.0, kGamma2 = 2.0;
 constexpr double kKappa = 2.0 / 3.0 + kGamma1 / 2.0 + kGamma2 / 3.0;
 constexpr int kRedBlocks = 240;
 
-size_t elem_size(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
+// bytes of one f value and of one g value as stored
+size_t f_size(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP16S ? 2 : 4); }
+size_t g_size(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
@@ -50,8 +52,7 @@ Layout layout_of(int nx, int ny, int prec)
     // x boundary (periodic needs ceil(nx / 60), walled ceil((nx - 2) / 60))
     L.pitch = ((nx + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS) * lbm::REGION_SLOTS;
     L.plane = (long long)(ny + 2) * L.pitch;
-    const size_t es = elem_size(prec);
-    L.buf_bytes = round_up(size_t(18) * L.plane * es, 256);
+    L.buf_bytes = round_up(size_t(9) * L.plane * (f_size(prec) + g_size(prec)), 256);
     L.macro_bytes = round_up(size_t(5) * nx * ny * sizeof(double), 256);
     L.flag_bytes = 256;
     L.total = 2 * L.buf_bytes + L.macro_bytes + L.flag_bytes;
@@ -193,7 +194,7 @@ lbm_status validate(lbm_ctx* c, int nx, int ny, const lbm_eos* eos, double Pr, d
     if (relax->law == LBM_VISC_SUTHERLAND && !(relax->sutherland_S >= 0))
         return fail(c, LBM_EINVAL, "Sutherland S must be >= 0");
     if (bc->extrap_order < 1 || bc->extrap_order > 2) return fail(c, LBM_EINVAL, "extrap_order must be 1 or 2");
-    if (opt->prec < 0 || opt->prec > 2) return fail(c, LBM_EINVAL, "unknown precision");
+    if (opt->prec < 0 || opt->prec > 3) return fail(c, LBM_EINVAL, "unknown precision");
     if (opt->cubic < 0 || opt->cubic > 2) return fail(c, LBM_EINVAL, "cubic must be 0, 1 or 2");
     for (int s = 0; s < 4; ++s) {
         const lbm_side& sd = bc->side[s];
@@ -471,7 +472,7 @@ extern "C" {
 
 size_t lbm_workspace_bytes(int nx, int ny, int prec)
 {
-    if (nx < 1 || ny < 1 || prec < 0 || prec > 2) return 0;
+    if (nx < 1 || ny < 1 || prec < 0 || prec > 3) return 0;
     return layout_of(nx, ny, prec).total;
 }
 

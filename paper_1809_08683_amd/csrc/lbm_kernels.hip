@@ -34,22 +34,41 @@ namespace lbm {
 constexpr int WAVE = 64;
 constexpr int WAVES_PER_BLOCK = 4;
 
+// Storage format of the DFs: element type of the nine f rows and of the
+// nine g rows of a stored row block (both decode to the arithmetic type C).
+template <typename SF, typename SG>
+struct Format {
+    using F = SF;
+    using G = SG;
+    using C = typename Store<SF>::C;
+    static_assert(sizeof(typename Store<SG>::C) == sizeof(C), "f and g rows share one arithmetic type");
+    static constexpr int EF = int(sizeof(SF)), EG = int(sizeof(SG));
+};
+using FmtF64 = Format<double, double>;
+using FmtF32 = Format<float, float>;
+using FmtF16 = Format<__half, __half>;
+using FmtF32G16 = Format<float, __half>;
+
 // Per storage format: the wavefronts per SIMD that the register budget of
 // the step kernel allows; whether the interior waves of a block advance row
 // by row together (a barrier per row, so that the edge lanes of neighbouring
 // strips read the lines their neighbours fetch at the same moment); whether
 // the strips next to an x-wall select the wall state of their wall lanes
 // instead of branching (needs a few more registers).
-template <typename S> struct Tuning;
-template <> struct Tuning<double> {
+template <typename Fm> struct Tuning;
+template <> struct Tuning<FmtF64> {
     static constexpr int waves = 2;
     static constexpr bool lockstep = true, edge_select = true;
 };
-template <> struct Tuning<float> {
+template <> struct Tuning<FmtF32> {
     static constexpr int waves = 3;
     static constexpr bool lockstep = true, edge_select = true;
 };
-template <> struct Tuning<__half> {
+template <> struct Tuning<FmtF32G16> {
+    static constexpr int waves = 3;
+    static constexpr bool lockstep = true, edge_select = true;
+};
+template <> struct Tuning<FmtF16> {
     static constexpr int waves = 4;
     static constexpr bool lockstep = false, edge_select = false;
 };
@@ -108,16 +127,42 @@ __device__ __forceinline__ void for_each_slot(const CaseParams& P, int x, F&& fn
     }
 }
 
-// element index of stored row block y (row y + 1) and DF q
-__device__ __forceinline__ long long row_index(const CaseParams& P, int q, int y)
+// Bytes of one stored row block and the byte offset of DF row q (0..17)
+// inside it: the nine f rows, then the nine g rows.
+template <typename Fm>
+__device__ __forceinline__ long long block_bytes(const CaseParams& P)
 {
-    return ((long long)(wrap_axis(y, P.ny, P.wall_y) + 1) * 18 + q) * P.pitch;
+    return 9LL * P.pitch * (Fm::EF + Fm::EG);
+}
+template <typename Fm>
+__device__ __forceinline__ long long row_offset(const CaseParams& P, int q)
+{
+    return q < 9 ? (long long)q * P.pitch * Fm::EF : 9LL * P.pitch * Fm::EF + (long long)(q - 9) * P.pitch * Fm::EG;
 }
 
-// element index of DF q (0..17) of node (x, y), x in [-1, nx], y in [-1, ny]
-__device__ __forceinline__ long long df_index(const CaseParams& P, int q, int x, int y)
+// byte offset of DF row q of lattice row y in [-1, ny] (stored row y + 1)
+template <typename Fm>
+__device__ __forceinline__ long long row_byte(const CaseParams& P, int q, int y)
 {
-    return row_index(P, q, y) + col_slot(P, x);
+    return (long long)(wrap_axis(y, P.ny, P.wall_y) + 1) * block_bytes<Fm>(P) + row_offset<Fm>(P, q);
+}
+
+template <typename Fm> __device__ __forceinline__ typename Fm::C load_df(const char* buf, int q, long long off)
+{
+    using F = typename Fm::F;
+    using G = typename Fm::G;
+    return q < 9 ? Store<F>::load(reinterpret_cast<const F*>(buf + off)) : Store<G>::load(reinterpret_cast<const G*>(buf + off));
+}
+template <typename Fm> __device__ __forceinline__ void store_df(char* buf, int q, long long off, typename Fm::C v)
+{
+    using F = typename Fm::F;
+    using G = typename Fm::G;
+    if (q < 9) Store<F>::store(reinterpret_cast<F*>(buf + off), v);
+    else Store<G>::store(reinterpret_cast<G*>(buf + off), v);
+}
+template <typename Fm> __device__ __forceinline__ long long slot_bytes(int q, int slot)
+{
+    return (long long)slot * (q < 9 ? Fm::EF : Fm::EG);
 }
 
 // side indices of a node: x-side (0/1) or -1, y-side (2/3) or -1
@@ -149,47 +194,52 @@ __device__ __forceinline__ double node_state(const CaseParams& P, const Coef<C>&
 }
 
 // Pull the 18 DFs of node (x, y) (generic indexing) and take their moments.
-template <typename S, typename C>
-__device__ __forceinline__ void pull_node(const CaseParams& P, const S* src, int x, int y, C m[9], C n[9])
+template <typename Fm>
+__device__ __forceinline__ void pull_node(const CaseParams& P, const char* src, int x, int y,
+                                          typename Fm::C m[9], typename Fm::C n[9])
 {
+    using C = typename Fm::C;
     C f[9], g[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        f[q] = Store<S>::load(src + df_index(P, q, x - EXq(q), y - EYq(q)));
-        g[q] = Store<S>::load(src + df_index(P, 9 + q, x - EXq(q), y - EYq(q)));
+        const int sx = x - EXq(q), sy = y - EYq(q);
+        const int slot = col_slot(P, sx);
+        f[q] = load_df<Fm>(src, q, row_byte<Fm>(P, q, sy) + slot_bytes<Fm>(q, slot));
+        g[q] = load_df<Fm>(src, 9 + q, row_byte<Fm>(P, 9 + q, sy) + slot_bytes<Fm>(9 + q, slot));
     }
     to_moments<C>(f, m);
     to_moments<C>(g, n);
 }
 
 // store the 18 DFs of node (x, y) into every slot that holds its column
-template <typename S>
-__device__ __forceinline__ void store_node(const CaseParams& P, S* dst, int x, int y,
-                                           const typename Store<S>::C fb[9], const typename Store<S>::C gb[9])
+template <typename Fm>
+__device__ __forceinline__ void store_node(const CaseParams& P, char* dst, int x, int y,
+                                           const typename Fm::C fb[9], const typename Fm::C gb[9])
 {
     for_each_slot(P, x, [&](int slot) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            Store<S>::store(dst + row_index(P, q, y) + slot, fb[q]);
-            Store<S>::store(dst + row_index(P, 9 + q, y) + slot, gb[q]);
+            store_df<Fm>(dst, q, row_byte<Fm>(P, q, y) + slot_bytes<Fm>(q, slot), fb[q]);
+            store_df<Fm>(dst, 9 + q, row_byte<Fm>(P, 9 + q, y) + slot_bytes<Fm>(9 + q, slot), gb[q]);
         }
     });
 }
 
 // Write the post-collision DFs of a wall node that leave the domain into the
-// ghost cells they reach, in the plane of the opposite direction.
-template <typename S>
-__device__ __forceinline__ void store_ghosts(const CaseParams& P, S* dst, int x, int y,
-                                             const typename Store<S>::C fb[9], const typename Store<S>::C gb[9])
+// ghost cells they reach, in the row of the opposite direction.
+template <typename Fm>
+__device__ __forceinline__ void store_ghosts(const CaseParams& P, char* dst, int x, int y,
+                                             const typename Fm::C fb[9], const typename Fm::C gb[9])
 {
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
         const int tx = x + EXq(q), ty = y + EYq(q);
         const bool out = (P.wall_x && (tx < 0 || tx >= P.nx)) || (P.wall_y && (ty < 0 || ty >= P.ny));
         if (out) {
+            const int qf = OPPq(q), qg = 9 + OPPq(q);
             for_each_slot(P, tx, [&](int slot) {
-                Store<S>::store(dst + row_index(P, OPPq(q), ty) + slot, fb[q]);
-                Store<S>::store(dst + row_index(P, 9 + OPPq(q), ty) + slot, gb[q]);
+                store_df<Fm>(dst, qf, row_byte<Fm>(P, qf, ty) + slot_bytes<Fm>(qf, slot), fb[q]);
+                store_df<Fm>(dst, qg, row_byte<Fm>(P, qg, ty) + slot_bytes<Fm>(qg, slot), gb[q]);
             });
         }
     }
@@ -333,14 +383,16 @@ __device__ __forceinline__ int stored_row(int v, int n, int walled)
 // be written get an offset past the record count, which the hardware drops,
 // so the loads of row y + 2 stay in flight across the collision and the
 // stores of row y.
-template <typename S, bool EXPORT>
-__device__ __forceinline__ void interior_item(const CaseParams& P, const WorkItem w, const S* __restrict__ src_in,
-                                              S* __restrict__ dst_in)
+template <typename Fm, bool EXPORT>
+__device__ __forceinline__ void interior_item(const CaseParams& P, const WorkItem w, const char* __restrict__ src_in,
+                                              char* __restrict__ dst_in)
 {
-    const S* __restrict__ src = uniform_ptr(src_in);
-    S* __restrict__ dst = uniform_ptr(dst_in);
-    using C = typename Store<S>::C;
-    constexpr int ES = int(sizeof(S));
+    const char* __restrict__ src = uniform_ptr(src_in);
+    char* __restrict__ dst = uniform_ptr(dst_in);
+    using C = typename Fm::C;
+    using F = typename Fm::F;
+    using G = typename Fm::G;
+    constexpr int EF = Fm::EF, EG = Fm::EG;
     const Coef<C>& K = coef<C>(P);
     const int lane = threadIdx.x & (WAVE - 1);
     const int nx = P.nx, ny = P.ny, pitch = P.pitch;
@@ -356,19 +408,23 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     // byte offset of the slot a pull along e_x reads: inside the own region
     // for source columns X - 1 .. X + 60 (own columns and the two copies, or
     // the wall and ghost slots on a walled side), the owning slot otherwise
-    auto src_off = [&](int ex) {
+    auto src_slot = [&](int ex) {
         const int d = c - ex, p = d - (X - 2);
         const bool inside = regular && p >= 1 && p <= REGION_SLOTS - 2 && (!wall_x || (d >= -1 && d <= nx));
-        return (inside ? region + p : col_slot(P, cn - ex)) * ES;
+        return inside ? region + p : col_slot(P, cn - ex);
     };
-    const int vo0 = src_off(1), vo1 = src_off(0), vo2 = src_off(-1);
+    const int sl0 = src_slot(1), sl1 = src_slot(0), sl2 = src_slot(-1);
+    // per-lane byte offsets in f rows and in g rows (the same when both use one type)
+    const int vf0 = sl0 * EF, vf1 = sl1 * EF, vf2 = sl2 * EF;
+    const int vg0 = sl0 * EG, vg1 = sl1 * EG, vg2 = sl2 * EG;
     // slots this lane stores: all but the wall and ghost slots of a walled side
     const bool keep = wall_x && (c == -1 || c == 0 || c == nx - 1 || c == nx);
-    const int vo_out = keep ? kDropOffset : (region + lane) * ES;
+    const int vf_out = keep ? kDropOffset : (region + lane) * EF;
+    const int vg_out = keep ? kDropOffset : (region + lane) * EG;
     const bool out_lane = lane >= 2 && lane < 2 + STRIP_COLS && c < xhi;   // own nodes
-    const int row_bytes = pitch * ES;
-    const unsigned blk_bytes = unsigned(18 * row_bytes);
-    const long long blk = 18LL * pitch;
+    const int frow_bytes = pitch * EF, grow_bytes = pitch * EG, g_base = 9 * frow_bytes;
+    const unsigned blk_bytes = unsigned(9 * (frow_bytes + grow_bytes));
+    const long long blk = blk_bytes;
     const int ylast = w.y0 + w.len - 1;
 
     // pull lattice row yy: DF q comes from (x - e_qx, yy - e_qy)
@@ -379,20 +435,21 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             const rsrc_t r = EYq(q) == 1 ? r_s : (EYq(q) == 0 ? r_c : r_n);
-            const int v = EXq(q) == 1 ? vo0 : (EXq(q) == 0 ? vo1 : vo2);
-            f[q] = Store<S>::bload(r, v, q * row_bytes);
-            g[q] = Store<S>::bload(r, v, (9 + q) * row_bytes);
+            const int vf = EXq(q) == 1 ? vf0 : (EXq(q) == 0 ? vf1 : vf2);
+            const int vg = EXq(q) == 1 ? vg0 : (EXq(q) == 0 ? vg1 : vg2);
+            f[q] = Store<F>::bload(r, vf, q * frow_bytes);
+            g[q] = Store<G>::bload(r, vg, g_base + q * grow_bytes);
         }
     };
     // A strip next to an x-wall has lanes on the wall column; their state
     // takes the wall velocity / temperature by selection (no divergence).
-    const bool edge = Tuning<S>::edge_select && wall_x && (X - 2 <= 0 || X + REGION_SLOTS - 3 >= nx - 1);
+    const bool edge = Tuning<Fm>::edge_select && wall_x && (X - 2 <= 0 || X + REGION_SLOTS - 3 >= nx - 1);
     // moments and state of a pulled row (wall rows: uniform branch to the wall formulas)
     auto row_state = [&](int yy, const C f[9], const C g[9], C dm[9], C dn[9], NodeState<C>& st) {
         to_moments<C>(f, dm);
         to_moments<C>(g, dn);
         const int sy = side_y(P, stored_row(yy, ny, wall_y) - 1);
-        if (sy >= 0 || !Tuning<S>::edge_select) return node_state<C>(P, K, sx, sy, dm, dn[0], st);
+        if (sy >= 0 || !Tuning<Fm>::edge_select) return node_state<C>(P, K, sx, sy, dm, dn[0], st);
         if (edge) {
             const bool right = sx == 1;
             const bool dir = sx >= 0 && !(right ? P.side_adiabatic[1] : P.side_adiabatic[0]);
@@ -420,7 +477,7 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     }
 
     for (int y = y0; y <= ylast; ++y) {
-        if constexpr (Tuning<S>::lockstep) __syncthreads();
+        if constexpr (Tuning<Fm>::lockstep) __syncthreads();
         progress_priority(y - y0, w.len);
         // loads of row y + 2 (on the last row a repeat of row y + 1, which
         // is in cache and whose state is not used) before the collision
@@ -446,8 +503,8 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
         const rsrc_t ro = make_rsrc(dst + (long long)(y + 1) * blk, blk_bytes);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            Store<S>::bstore(ro, vo_out, q * row_bytes, fb[q]);
-            Store<S>::bstore(ro, vo_out, (9 + q) * row_bytes, gb[q]);
+            Store<F>::bstore(ro, vf_out, q * frow_bytes, fb[q]);
+            Store<G>::bstore(ro, vg_out, g_base + q * grow_bytes, gb[q]);
         }
         if (EXPORT && out_lane) export_node<C>(P, c, y, s_c, K.T0_d + double(s_c.dT));
         rho_m = s_c.drho;
@@ -490,14 +547,14 @@ __device__ __forceinline__ void wall_node_xy(const CaseParams& P, int i, int& x,
     y = ylo + i;
 }
 
-template <typename S>
-__device__ __forceinline__ typename Store<S>::C node_rho_p(const CaseParams& P, const S* src, int x, int y,
-                                                          typename Store<S>::C& p)
+template <typename Fm>
+__device__ __forceinline__ typename Fm::C node_rho_p(const CaseParams& P, const char* src, int x, int y,
+                                                    typename Fm::C& p)
 {
-    using C = typename Store<S>::C;
+    using C = typename Fm::C;
     C m[9], n[9];
     NodeState<C> s;
-    pull_node<S, C>(P, src, x, y, m, n);
+    pull_node<Fm>(P, src, x, y, m, n);
     const int xw = wrap_axis(x, P.nx, P.wall_x), yw = wrap_axis(y, P.ny, P.wall_y);
     node_state<C>(P, coef<C>(P), side_x(P, xw), side_y(P, yw), m, n[0], s);
     p = s.dp;
@@ -507,28 +564,28 @@ __device__ __forceinline__ typename Store<S>::C node_rho_p(const CaseParams& P, 
 // derivative of rho and p (as deviations) along one axis at a wall node (second-order
 // one-sided towards the inside along a walled axis it lies on, two-point
 // central otherwise)
-template <typename S>
-__device__ __forceinline__ void wall_axis_gradient(const CaseParams& P, const S* src, int x, int y, int ax,
-                                                   typename Store<S>::C rho0, typename Store<S>::C p0,
-                                                   typename Store<S>::C& gr, typename Store<S>::C& gp)
+template <typename Fm>
+__device__ __forceinline__ void wall_axis_gradient(const CaseParams& P, const char* src, int x, int y, int ax,
+                                                   typename Fm::C rho0, typename Fm::C p0,
+                                                   typename Fm::C& gr, typename Fm::C& gp)
 {
-    using C = typename Store<S>::C;
+    using C = typename Fm::C;
     const int dx = ax == 0 ? 1 : 0, dy = ax == 0 ? 0 : 1;
     const int s = ax == 0 ? side_x(P, x) : side_y(P, y);
     C p1, p2;
     if (s == 0 || s == 2) {
-        const C r1 = node_rho_p<S>(P, src, x + dx, y + dy, p1);
-        const C r2 = node_rho_p<S>(P, src, x + 2 * dx, y + 2 * dy, p2);
+        const C r1 = node_rho_p<Fm>(P, src, x + dx, y + dy, p1);
+        const C r2 = node_rho_p<Fm>(P, src, x + 2 * dx, y + 2 * dy, p2);
         gr = (C(-3) * rho0 + C(4) * r1 - r2) * C(0.5);
         gp = (C(-3) * p0 + C(4) * p1 - p2) * C(0.5);
     } else if (s == 1 || s == 3) {
-        const C r1 = node_rho_p<S>(P, src, x - dx, y - dy, p1);
-        const C r2 = node_rho_p<S>(P, src, x - 2 * dx, y - 2 * dy, p2);
+        const C r1 = node_rho_p<Fm>(P, src, x - dx, y - dy, p1);
+        const C r2 = node_rho_p<Fm>(P, src, x - 2 * dx, y - 2 * dy, p2);
         gr = (C(3) * rho0 - C(4) * r1 + r2) * C(0.5);
         gp = (C(3) * p0 - C(4) * p1 + p2) * C(0.5);
     } else {
-        const C r1 = node_rho_p<S>(P, src, x + dx, y + dy, p1);
-        const C r2 = node_rho_p<S>(P, src, x - dx, y - dy, p2);
+        const C r1 = node_rho_p<Fm>(P, src, x + dx, y + dy, p1);
+        const C r2 = node_rho_p<Fm>(P, src, x - dx, y - dy, p2);
         gr = (r1 - r2) * C(0.5);
         gp = (p1 - p2) * C(0.5);
     }
@@ -536,15 +593,15 @@ __device__ __forceinline__ void wall_axis_gradient(const CaseParams& P, const S*
 
 // Tilde non-equilibrium moments of an off-wall node (eq. neq.redefinition):
 //   Zm = (I - S/2) m^neq,  Zn = (I - L/2) n^neq + (Y/2) Zm
-template <typename S>
-__device__ __forceinline__ void tilde_at(const CaseParams& P, const S* src, int x, int y,
-                                         typename Store<S>::C Zm[9], typename Store<S>::C Zn[9])
+template <typename Fmt>
+__device__ __forceinline__ void tilde_at(const CaseParams& P, const char* src, int x, int y,
+                                         typename Fmt::C Zm[9], typename Fmt::C Zn[9])
 {
-    using C = typename Store<S>::C;
+    using C = typename Fmt::C;
     const Coef<C>& K = coef<C>(P);
     C m[9], n[9];
     NodeState<C> s;
-    pull_node<S, C>(P, src, x, y, m, n);
+    pull_node<Fmt>(P, src, x, y, m, n);
     node_state<C>(P, K, -1, -1, m, n[0], s);
     Rates<C> r;
     local_rates<C>(K, P.visc_law, s, r);
@@ -563,11 +620,11 @@ __device__ __forceinline__ void tilde_at(const CaseParams& P, const S* src, int 
     Zn[6] -= C(0.5) * y5;
 }
 
-template <typename S, bool EXPORT>
-__device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w, const S* __restrict__ src,
-                          S* __restrict__ dst)
+template <typename Fmt, bool EXPORT>
+__device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w, const char* __restrict__ src,
+                                          char* __restrict__ dst)
 {
-    using C = typename Store<S>::C;
+    using C = typename Fmt::C;
     const Coef<C>& K = coef<C>(P);
     const int lane = threadIdx.x & (WAVE - 1);
     if (lane >= w.len) return;
@@ -578,17 +635,17 @@ __device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w,
     // macros of the wall node from the bounce-back completed DFs (Sec. 3.1)
     C m[9], n[9];
     NodeState<C> s;
-    pull_node<S, C>(P, src, xb, yb, m, n);
+    pull_node<Fmt>(P, src, xb, yb, m, n);
     const double T_d = node_state<C>(P, K, sx, sy, m, n[0], s);
 
     // extrapolated tilde non-equilibrium moments (eq. neq.extrapolation)
     const int ndx = sx == 0 ? 1 : (sx == 1 ? -1 : 0);
     const int ndy = sy == 2 ? 1 : (sy == 3 ? -1 : 0);
     C Zm[9], Zn[9];
-    tilde_at<S>(P, src, xb + ndx, yb + ndy, Zm, Zn);
+    tilde_at<Fmt>(P, src, xb + ndx, yb + ndy, Zm, Zn);
     if (P.extrap_order == 2) {
         C Zm2[9], Zn2[9];
-        tilde_at<S>(P, src, xb + 2 * ndx, yb + 2 * ndy, Zm2, Zn2);
+        tilde_at<Fmt>(P, src, xb + 2 * ndx, yb + 2 * ndy, Zm2, Zn2);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             Zm[q] = C(2) * Zm[q] - Zm2[q];
@@ -619,8 +676,8 @@ __device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w,
 
     // gradients at the wall node
     C gr_x, gr_y, gp_x, gp_y;
-    wall_axis_gradient<S>(P, src, xb, yb, 0, s.drho, s.dp, gr_x, gp_x);
-    wall_axis_gradient<S>(P, src, xb, yb, 1, s.drho, s.dp, gr_y, gp_y);
+    wall_axis_gradient<Fmt>(P, src, xb, yb, 0, s.drho, s.dp, gr_x, gp_x);
+    wall_axis_gradient<Fmt>(P, src, xb, yb, 1, s.drho, s.dp, gr_y, gp_y);
 
     const Forcing<C> F = forcing<C>(K, P.per_mass, s);
     C meq[9], Fm[9], neq[9], Qm[9], mb[9], nb[9], fb[9], gb[9];
@@ -631,8 +688,8 @@ __device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w,
     post_collision<C>(s, r, P.cubic, meq, Fm, N, Zm, neq, Qm, Hm, Ht, gr_x, gr_y, gp_x, gp_y, mb, nb);
     from_moments<C>(mb, fb);
     from_moments<C>(nb, gb);
-    store_node<S>(P, dst, xb, yb, fb, gb);
-    store_ghosts<S>(P, dst, xb, yb, fb, gb);
+    store_node<Fmt>(P, dst, xb, yb, fb, gb);
+    store_ghosts<Fmt>(P, dst, xb, yb, fb, gb);
     if (EXPORT) export_node<C>(P, xb, yb, s, T_d);
 }
 
@@ -645,9 +702,9 @@ __device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w,
 
 // EXPORT: also write the macros of the new time level and the divergence
 // flag (the last step of a call).
-template <typename S, bool EXPORT>
+template <typename Fm, bool EXPORT>
 __global__ __launch_bounds__(WAVE * WAVES_PER_BLOCK)
-__attribute__((amdgpu_waves_per_eu(Tuning<S>::waves, 8))) void step_kernel(
+__attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
     const CaseParams* __restrict__ cases, const WorkItem* __restrict__ work, int nwork, int parity)
 {
     const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6));
@@ -667,9 +724,9 @@ __attribute__((amdgpu_waves_per_eu(Tuning<S>::waves, 8))) void step_kernel(
     progress_priority(0, 1);
     const CaseParams& P = *(const CaseParams*)(((const __attribute__((address_space(4))) CaseParams*)cases) + w.case_id);
     if (w.kind == 0)
-        interior_item<S, EXPORT>(P, w, static_cast<const S*>(P.buf[parity]), static_cast<S*>(P.buf[parity ^ 1]));
+        interior_item<Fm, EXPORT>(P, w, static_cast<const char*>(P.buf[parity]), static_cast<char*>(P.buf[parity ^ 1]));
     else
-        wall_item<S, EXPORT>(P, w, static_cast<const S*>(P.buf[parity]), static_cast<S*>(P.buf[parity ^ 1]));
+        wall_item<Fm, EXPORT>(P, w, static_cast<const char*>(P.buf[parity]), static_cast<char*>(P.buf[parity ^ 1]));
 }
 
 // ---------------------------------------------------------------------------
@@ -697,11 +754,11 @@ __device__ __forceinline__ void init_rho_p(const CaseParams& P, const Coef<C>& K
     p = C(eos_pressure_d<C>(K, P.eos, fld[i], fld[3 * nn + i]) - K.p0_d);
 }
 
-template <typename S>
+template <typename Fmt>
 __global__ __launch_bounds__(256) void init_kernel(const CaseParams* __restrict__ cases, int case_id,
                                                    const double* __restrict__ fld, int parity)
 {
-    using C = typename Store<S>::C;
+    using C = typename Fmt::C;
     const CaseParams& P = cases[case_id];
     const Coef<C>& K = coef<C>(P);
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -761,9 +818,9 @@ __global__ __launch_bounds__(256) void init_kernel(const CaseParams* __restrict_
     post_collision<C>(s, r, P.cubic, meq, Fm, Z, Z, neq, Qm, Z, Z, gr[0], gr[1], gp[0], gp[1], mb, nb);
     from_moments<C>(mb, fb);
     from_moments<C>(nb, gb);
-    S* dst = static_cast<S*>(P.buf[parity]);
-    store_node<S>(P, dst, x, y, fb, gb);
-    if (sx >= 0 || sy >= 0) store_ghosts<S>(P, dst, x, y, fb, gb);
+    char* dst = static_cast<char*>(P.buf[parity]);
+    store_node<Fmt>(P, dst, x, y, fb, gb);
+    if (sx >= 0 || sy >= 0) store_ghosts<Fmt>(P, dst, x, y, fb, gb);
     export_node<C>(P, x, y, s, T_d);
 }
 
@@ -891,75 +948,60 @@ int launch_copy(const void* src, void* dst, long long bytes, hipStream_t stream)
     return int(hipGetLastError());
 }
 
+// Calls fn with a value of the storage format of a precision code.
+template <typename Fn>
+int with_format(int prec, Fn&& fn)
+{
+    switch (prec) {
+    case PREC_F64: return fn(FmtF64{});
+    case PREC_F32: return fn(FmtF32{});
+    case PREC_F32G16: return fn(FmtF32G16{});
+    default: return fn(FmtF16{});
+    }
+}
+
 int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
                 int export_macros, hipStream_t stream)
 {
     const dim3 block(WAVE * WAVES_PER_BLOCK);
     const dim3 grid((nwork + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
     if (nwork == 0) return 0;
-    switch (prec * 2 + (export_macros ? 1 : 0)) {
-    case PREC_F64 * 2:
-        hipLaunchKernelGGL((step_kernel<double, false>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
-        break;
-    case PREC_F64 * 2 + 1:
-        hipLaunchKernelGGL((step_kernel<double, true>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
-        break;
-    case PREC_F32 * 2:
-        hipLaunchKernelGGL((step_kernel<float, false>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
-        break;
-    case PREC_F32 * 2 + 1:
-        hipLaunchKernelGGL((step_kernel<float, true>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
-        break;
-    case PREC_F16S * 2:
-        hipLaunchKernelGGL((step_kernel<__half, false>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
-        break;
-    default:
-        hipLaunchKernelGGL((step_kernel<__half, true>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
-        break;
-    }
-    return int(hipGetLastError());
+    return with_format(prec, [&](auto fm) {
+        using Fm = decltype(fm);
+        if (export_macros)
+            hipLaunchKernelGGL((step_kernel<Fm, true>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
+        else
+            hipLaunchKernelGGL((step_kernel<Fm, false>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
+        return int(hipGetLastError());
+    });
 }
 
 // Whether the interior waves of a block march in lockstep (the work list
 // then keeps wall items out of interior blocks).
 int step_lockstep(int prec)
 {
-    switch (prec) {
-    case PREC_F64: return Tuning<double>::lockstep;
-    case PREC_F32: return Tuning<float>::lockstep;
-    default: return Tuning<__half>::lockstep;
-    }
+    return with_format(prec, [](auto fm) { return int(Tuning<decltype(fm)>::lockstep); });
 }
 
 // Resident 256-thread blocks of the step kernel per CU for a precision.
 int step_blocks_per_cu(int prec)
 {
-    int n = 0;
-    hipError_t e;
-    switch (prec) {
-    case PREC_F64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<double, false>, WAVE * WAVES_PER_BLOCK, 0); break;
-    case PREC_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, false>, WAVE * WAVES_PER_BLOCK, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<__half, false>, WAVE * WAVES_PER_BLOCK, 0); break;
-    }
-    return e == hipSuccess ? n : 0;
+    return with_format(prec, [](auto fm) {
+        int n = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<decltype(fm), false>,
+                                                                          WAVE * WAVES_PER_BLOCK, 0);
+        return e == hipSuccess ? n : 0;
+    });
 }
 
 int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
                 int parity, hipStream_t stream)
 {
     const dim3 grid(unsigned((nodes + 255) / 256)), block(256);
-    switch (prec) {
-    case PREC_F64:
-        hipLaunchKernelGGL(init_kernel<double>, grid, block, 0, stream, d_cases, case_id, d_fields, parity);
-        break;
-    case PREC_F32:
-        hipLaunchKernelGGL(init_kernel<float>, grid, block, 0, stream, d_cases, case_id, d_fields, parity);
-        break;
-    default:
-        hipLaunchKernelGGL(init_kernel<__half>, grid, block, 0, stream, d_cases, case_id, d_fields, parity);
-        break;
-    }
-    return int(hipGetLastError());
+    return with_format(prec, [&](auto fm) {
+        hipLaunchKernelGGL((init_kernel<decltype(fm)>), grid, block, 0, stream, d_cases, case_id, d_fields, parity);
+        return int(hipGetLastError());
+    });
 }
 
 int launch_totals(const CaseParams* d_cases, int case_id, double* d_partial, int nblocks, double* d_out,

@@ -7,7 +7,7 @@ namespace lbm {
 
 enum { EOS_DECOUPLED = 0, EOS_IDEAL = 1, EOS_VDW = 2, EOS_CS = 3 };
 enum { VISC_CONST = 0, VISC_LINEAR = 1, VISC_SUTHERLAND = 2 };
-enum { PREC_F64 = 0, PREC_F32 = 1, PREC_F16S = 2 };
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_F16S = 2, PREC_F32G16 = 3 };
 
 // Constants of one case in one compute type.
 template <typename C>

@@ -142,15 +142,45 @@ def cavity(N=512, Ra=1e6, eps=0.6, Pr=0.71, nu0=0.1, Ma=None, bulk_ratio=None, n
     return c
 
 
-def batch_cases(seed=2, n=64, Ma=0.05, nu_min=0.1, prec="f32") -> list:
+def stable_nu0_window(eps: float, Pr: float, smax: float = 1.85, suth_S: float = 110.5 / 600.0):
+    """Range of nu0 = mu0/rho0 for which the relaxation rates that the fixed
+    products of Sec. 4 pair up stay at or below smax at both walls of a
+    cavity with T = T0 (1 +- eps), isobaric density rho0 T0 / T and
+    Sutherland viscosity:
+      cold wall (small nu): s_p <= smax and sigma_j <= smax,
+      hot wall (large nu):  s_q <= smax and sigma_e <= smax,
+    using 1/s_p - 1/2 = 3 nu, (1/s_p - 1/2)(1/s_q - 1/2) = 1/12,
+    1/sigma_j - 1/2 = nu / (kappa Pr) (rho = rho0), (1/sigma_j - 1/2)
+    (1/sigma_e - 1/2) = 1/4, kappa = 1/3.  Returns (lo, hi); lo > hi when
+    no such window exists."""
+    kappa = 1.0 / 3.0
+    m = 1.0 / smax - 0.5                       # required 1/s - 1/2 margin
+
+    def nu_factor(T):                         # nu(T) / nu0 at p = p0
+        mu = T ** 1.5 * (1.0 + suth_S) / (T + suth_S)
+        return mu * T                          # mu / rho with rho = 1 / T
+    fc, fh = nu_factor(1.0 - eps), nu_factor(1.0 + eps)
+    mu_c = (1.0 - eps) ** 1.5 * (1.0 + suth_S) / (1.0 - eps + suth_S)
+    mu_h = (1.0 + eps) ** 1.5 * (1.0 + suth_S) / (1.0 + eps + suth_S)
+    lo = max(m / 3.0 / fc, m * kappa * Pr / mu_c)
+    hi = min((1.0 / 36.0) / m / fh, 0.25 * kappa * Pr / m / mu_h)
+    return lo, hi
+
+
+def batch_cases(seed=2, n=64, Ma=0.05, nu_min=0.1, smax=1.75, prec="f32") -> list:
     """Uneven cavities: N in {128,256,512,1024}, log10 Ra in U[3,8],
     eps in U[0.1,0.6], Pr in {0.71,1,7}; four draws per case from one stream.
 
     Each case is set up at buoyancy Mach number Ma (g and mu0 from Ra as in
-    cavity(Ma=...)).  Where that viscosity would fall below nu_min (the
-    scheme's linear stability limit at tau0 = 0.8) the case runs at nu_min
-    with the same g, i.e. at the lower effective Rayleigh number
-    Ra * (nu_Ma / nu_min)^2, recorded as "Ra_eff"."""
+    cavity(Ma=...)).  Where that viscosity falls outside the window
+    [max(nu_min, lo), hi] with (lo, hi) = stable_nu0_window(eps, Pr) it is
+    moved to the nearest end (the geometric mean if the window is empty)
+    with the same g, i.e. run at the effective Rayleigh number
+    Ra * (nu_Ma / nu0)^2, "Ra_eff".  nu_min = 0.1 (tau0 = 0.8) is where the
+    linearised coupled scheme stops growing at the cold wall of an eps = 0.6
+    cavity.  For Pr = 7 and eps >= 0.48 the window is empty (s_q at the hot
+    wall and sigma_j at the cold wall cannot both stay below smax); those
+    cases run at the geometric mean and diverge after a few hundred steps."""
     u = uniform01(seed, 4 * n).reshape(n, 4)
     sizes = (128, 256, 512, 1024)
     prs = (0.71, 1.0, 7.0)
@@ -162,10 +192,14 @@ def batch_cases(seed=2, n=64, Ma=0.05, nu_min=0.1, prec="f32") -> list:
         Pr = prs[min(int(u[k, 3] * 3), 2)]
         c = cavity(N=N, Ra=Ra, eps=eps, Pr=Pr, Ma=Ma, prec=prec)
         c["Ra_eff"] = Ra
-        if c["nu0"] < nu_min:
-            c["Ra_eff"] = Ra * (c["nu0"] / nu_min) ** 2
-            c["nu0"] = nu_min
-            c["Ma_ref"] = math.sqrt(c["Ra_eff"]) * nu_min / (N - 1) / math.sqrt(CS2)
+        lo, hi = stable_nu0_window(eps, Pr, smax)
+        lo = max(lo, nu_min)
+        nu = c["nu0"] if lo <= hi else math.sqrt(lo * hi)
+        nu = min(max(nu, lo), hi) if lo <= hi else nu
+        if nu != c["nu0"]:
+            c["Ra_eff"] = Ra * (c["nu0"] / nu) ** 2
+            c["nu0"] = nu
+            c["Ma_ref"] = math.sqrt(c["Ra_eff"]) * nu / (N - 1) / math.sqrt(CS2)
         out.append(c)
     return out
 

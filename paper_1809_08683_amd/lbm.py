@@ -18,8 +18,9 @@ LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
 OK, EINVAL, ENOMEM, EDEVICE, EDIVERGED, ESTATE = 0, -1, -2, -3, -4, -5
 EOS = {"decoupled": 0, "ideal": 1, "vdw": 2, "cs": 3}
 VISC = {"const": 0, "linear": 1, "sutherland": 2}
-PREC = {"f64": 0, "f32": 1, "f16s": 2}
-ELEM_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
+PREC = {"f64": 0, "f32": 1, "f16s": 2, "f32g16": 3}
+# bytes of one stored (f, g) value pair
+PAIR_BYTES = {"f64": 16, "f32": 8, "f16s": 4, "f32g16": 6}
 
 
 class LibraryMissing(RuntimeError):
@@ -199,9 +200,11 @@ class _Base:
         self._check(self.lib.lbm_step(self.h, int(n)), "lbm_step")
         return self
 
-    def step_timed(self, n: int) -> float:
+    def step_timed(self, n: int, allow_diverged: bool = False) -> float:
         ms = C.c_double(0.0)
-        self._check(self.lib.lbm_step_timed(self.h, int(n), C.byref(ms)), "lbm_step_timed")
+        rc = self.lib.lbm_step_timed(self.h, int(n), C.byref(ms))
+        if not (rc == EDIVERGED and allow_diverged):
+            self._check(rc, "lbm_step_timed")
         return ms.value
 
     @property

@@ -6,7 +6,8 @@ Bars:
     T and p (velocity components relative to the largest velocity component
     of the field);
   * FP32 path: 2e-5 for rho, T, p and 2e-4 for u after at most 50 steps;
-  * FP16 offset path: 2e-3 for rho, T, p and 2e-2 for u after at most 50 steps.
+  * FP16 offset path and the FP32-f / FP16-g path: 2e-3 for rho, T, p and
+    2e-2 for u after at most 50 steps.
 The FP32/FP16 bars follow from their unit roundoffs (6e-8 and 4.9e-4 on the
 stored offsets) times the number of rounded operations that feed one value
 over the steps of a test; the measured errors sit one to two orders below.
@@ -22,7 +23,7 @@ pytestmark = pytest.mark.gpu
 P = inputs._periodic
 W = inputs._side
 FIELDS = ("rho", "ux", "uy", "T", "p")
-BAR = {"f64": (1e-10, 1e-10), "f32": (2e-5, 2e-4), "f16s": (2e-3, 2e-2)}
+BAR = {"f64": (1e-10, 1e-10), "f32": (2e-5, 2e-4), "f16s": (2e-3, 2e-2), "f32g16": (2e-3, 2e-2)}
 
 
 def rel_err(a, b):
@@ -110,7 +111,7 @@ def test_fp64_parity_segment_heights(seg_rows):
     compare(g.macros(), o.macros(), "f64", f"seg_rows={seg_rows}")
 
 
-@pytest.mark.parametrize("prec", ["f32", "f16s"])
+@pytest.mark.parametrize("prec", ["f32", "f16s", "f32g16"])
 @pytest.mark.parametrize("name", ["periodic_gravity", "channel_couette", "cavity_order1", "cavity_ragged_strips_131x9"])
 def test_reduced_precision_parity_small(prec, name):
     g, o = run_pair(SMALL[name], 20, prec=prec)
@@ -174,7 +175,7 @@ def test_cavity_512_fp64_full_grid():
     compare(g.macros(), o.macros(), "f64", "cavity 512 x 20")
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s", "f32g16"])
 def test_cavity_2048_full_grid(prec):
     """2048^2 cavity (eps = 0.6, Ra = 1e8), 2 steps from random fields,
     every node compared with the oracle."""
@@ -284,16 +285,18 @@ def _nu_run(prec, steps):
 def test_nusselt_cavity_256_against_table2_and_fp64(golden):
     """256^2 cavity, Ra = 1e5, eps = 0.6 (Table 1 pairing), 100000 steps:
     the FP64 path reaches a steady mean hot-wall Nu within 1% of the value
-    Table 2 prints for this Rayleigh number (4.4836), and the FP32 path stays
-    within 0.5% of the FP64 path (whose every step matches the oracle to
-    1e-10 in the parity tests above).  The FP16-offset path is reported: its
-    16-bit density DFs limit it to about 10% here (see the design notes)."""
+    Table 2 prints for this Rayleigh number (4.4836), and the FP32 path and
+    the FP32-f / FP16-g path stay within 0.5% of the FP64 path (whose every
+    step matches the oracle to 1e-10 in the parity tests above).  The
+    FP16-offset path is reported: its 16-bit density DFs limit it to about
+    10% here."""
     t2 = golden["cavity_table2_present"]
     ref = t2["Nu_ave"][t2["Ra"].index(1e5)]
-    nu = {p: _nu_run(p, 100000) for p in ("f64", "f32", "f16s")}
+    nu = {p: _nu_run(p, 100000) for p in ("f64", "f32", "f32g16", "f16s")}
     rel = {p: (nu[p] - nu["f64"]) / nu["f64"] for p in nu}
     print("Nu", {p: round(v, 5) for p, v in nu.items()}, "rel vs f64", {p: f"{v:.1e}" for p, v in rel.items()},
           f"f64 vs Table 2: {(nu['f64'] - ref) / ref:.2e}", flush=True)
     assert abs(nu["f64"] - ref) / ref < 0.01
     assert abs(rel["f32"]) < 5e-3
+    assert abs(rel["f32g16"]) < 5e-3
     assert np.isfinite(nu["f16s"]) and abs(rel["f16s"]) < 0.25
