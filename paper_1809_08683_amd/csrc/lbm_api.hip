@@ -246,7 +246,8 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
 // into strips of 60 columns and each strip into segments of nearly equal
 // height; by default the number of segments is chosen so that all items of
 // a step are resident at once (one round of wavefronts).  Wall nodes are
-// split over at least one wavefront per CU (up to 64 nodes each).  Without
+// split over wavefronts in proportion to their cost, at least one per CU
+// (each wavefront takes its nodes 64 at a time).  Without
 // lockstep every wall wavefront goes to a block of its own, so that each CU
 // carries the same mix of wall and interior work; with lockstep the wall
 // wavefronts fill blocks of their own.  Block b runs on XCD b % 8; the
@@ -271,12 +272,18 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, bool locks
     }
     std::vector<lbm::WorkItem> wall, inner;
     if (total_wall > 0) {
-        // at most 64 nodes (one per lane) per wavefront, at least one
-        // wavefront per CU while that leaves 16 or more nodes to each
-        long long nw = (total_wall + 63) / 64;
+        // Wall wavefronts get the share of the slots that their work needs:
+        // a wall node costs about kWallCost interior nodes (its own pull, the
+        // pulls at x_f, x_ff and of its gradient neighbours, the inversions).
+        // At least one per CU while that leaves 16 or more nodes to each;
+        // a wavefront takes its nodes 64 at a time.
+        constexpr double kWallCost = 12.0;
+        const double interior = double(total_cells) * lbm::STRIP_COLS;
+        const double frac = kWallCost * double(total_wall) / (kWallCost * double(total_wall) + interior);
+        long long nw = (long long)std::llround(frac * double(capacity));
         nw = std::max(nw, std::min<long long>(cus, (total_wall + 15) / 16));
+        nw = std::max<long long>(nw, 1);
         const int chunk = int((total_wall + nw - 1) / nw);
-        if (chunk > 64) return false;
         for (int k = 0; k < nc; ++k)
             for (int b = 0; b < nwall[k]; b += chunk) wall.push_back({k, 1, b, 0, std::min(chunk, nwall[k] - b), 0});
     }

@@ -620,16 +620,15 @@ __device__ __forceinline__ void tilde_at(const CaseParams& P, const char* src, i
     Zn[6] -= C(0.5) * y5;
 }
 
+// One wall node (index i of the case's wall-node enumeration) per lane.
 template <typename Fmt, bool EXPORT>
-__device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w, const char* __restrict__ src,
+__device__ __forceinline__ void wall_node(const CaseParams& P, int i, const char* __restrict__ src,
                                           char* __restrict__ dst)
 {
     using C = typename Fmt::C;
     const Coef<C>& K = coef<C>(P);
-    const int lane = threadIdx.x & (WAVE - 1);
-    if (lane >= w.len) return;
     int xb, yb;
-    wall_node_xy(P, w.x0 + lane, xb, yb);
+    wall_node_xy(P, i, xb, yb);
     const int sx = side_x(P, xb), sy = side_y(P, yb);
 
     // macros of the wall node from the bounce-back completed DFs (Sec. 3.1)
@@ -691,6 +690,16 @@ __device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w,
     store_node<Fmt>(P, dst, xb, yb, fb, gb);
     store_ghosts<Fmt>(P, dst, xb, yb, fb, gb);
     if (EXPORT) export_node<C>(P, xb, yb, s, T_d);
+}
+
+// wall item: wall nodes [x0, x0 + len), 64 at a time
+template <typename Fmt, bool EXPORT>
+__device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w, const char* __restrict__ src,
+                                          char* __restrict__ dst)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (int base = 0; base < w.len; base += WAVE)
+        if (base + lane < w.len) wall_node<Fmt, EXPORT>(P, w.x0 + base + lane, src, dst);
 }
 
 // ---------------------------------------------------------------------------
