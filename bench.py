@@ -36,6 +36,35 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernel_source_sha():
+    import hashlib
+    import glob
+    src = os.path.join(ROOT, "paper_1809_08683_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(src, "*.hip")) + glob.glob(os.path.join(src, "*.hpp"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 step kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE record, if it was taken on the current
+    kernel sources; None otherwise."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_cavity2048_traffic.md")
+    try:
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("traffic_record:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if rec.get("source_sha") == kernel_source_sha():
+                        return rec["bytes_per_launch"]
+    except OSError:
+        pass
+    return None
+
+
 def time_path(case, prec, steps, warmup, seg_rows=0):
     import torch
     from paper_1809_08683_amd import lbm
@@ -188,7 +217,7 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(h["frac_hbm"], 4),
-            "traffic": None,
+            "traffic": measured_traffic() if head == "f32" else None,
         },
         "paths": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in paths.items()},
