@@ -306,7 +306,8 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, bool locks
             const int y0 = ylo + int((long long)rows * g / nseg);
             const int y1 = ylo + int((long long)rows * (g + 1) / nseg);
             if (y1 <= y0) continue;
-            for (int st = 0; st < strips; ++st) inner.push_back({k, 0, xlo + lbm::STRIP_COLS * st, y0, y1 - y0, 0});
+            for (int st = 0; st < strips; ++st)
+                inner.push_back({k, 0, xlo + lbm::STRIP_COLS * st, y0, y1 - y0, g & 1});
         }
     }
     // Wall item i goes to slot i / nblocks of block i % nblocks (one per block

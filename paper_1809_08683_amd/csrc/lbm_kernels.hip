@@ -54,23 +54,24 @@ using FmtF32G16 = Format<float, __half>;
 // by row together (a barrier per row, so that the edge lanes of neighbouring
 // strips read the lines their neighbours fetch at the same moment); whether
 // the strips next to an x-wall select the wall state of their wall lanes
-// instead of branching (needs a few more registers).
+// instead of branching (needs a few more registers); whether segments of a
+// band alternate their march direction (the 16-bit format spills with it).
 template <typename Fm> struct Tuning;
 template <> struct Tuning<FmtF64> {
     static constexpr int waves = 2;
-    static constexpr bool lockstep = true, edge_select = true;
+    static constexpr bool lockstep = true, edge_select = true, alternate = true;
 };
 template <> struct Tuning<FmtF32> {
     static constexpr int waves = 3;
-    static constexpr bool lockstep = true, edge_select = true;
+    static constexpr bool lockstep = true, edge_select = true, alternate = true;
 };
 template <> struct Tuning<FmtF32G16> {
     static constexpr int waves = 3;
-    static constexpr bool lockstep = true, edge_select = true;
+    static constexpr bool lockstep = true, edge_select = true, alternate = true;
 };
 template <> struct Tuning<FmtF16> {
     static constexpr int waves = 4;
-    static constexpr bool lockstep = false, edge_select = false;
+    static constexpr bool lockstep = false, edge_select = false, alternate = false;
 };
 static_assert(REGION_SLOTS == WAVE && STRIP_COLS == WAVE - 4, "one wavefront per strip region");
 
@@ -425,7 +426,7 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     const int frow_bytes = pitch * EF, grow_bytes = pitch * EG, g_base = 9 * frow_bytes;
     const unsigned blk_bytes = unsigned(9 * (frow_bytes + grow_bytes));
     const long long blk = blk_bytes;
-    const int ylast = w.y0 + w.len - 1;
+    const int ylast_row = w.y0 + w.len - 1;
 
     // pull lattice row yy: DF q comes from (x - e_qx, yy - e_qy)
     auto pull = [&](int yy, C f[9], C g[9]) {
@@ -459,44 +460,54 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
         return state_from_moments<C>(K, P.eos, P.per_mass, dm, dn[0], st);
     };
 
+    // March direction: segments alternate up (d = +1) and down (d = -1), so
+    // the two rows a segment boundary shares are pulled by both segments at
+    // the same moment (both at the start or both at the end of the step).
+    // "ahead" is the next row in the direction of the march, "behind" the
+    // previous one.
+    const int d = Tuning<Fm>::alternate && w.dir ? -1 : 1;
+    const int yf = d > 0 ? w.y0 : ylast_row;
     C m_c[9], n_c[9], m_n[9], n_n[9];
-    NodeState<C> s_c, s_n;
-    C rho_m, p_m;
-    const int y0 = w.y0;
+    NodeState<C> s_c, s_n;          // current row, row ahead
+    C rho_b, p_b;                   // row behind
     {
         C f[9], g[9], dm[9], dn[9];
         NodeState<C> st;
-        pull(y0 - 1, f, g);
-        row_state(y0 - 1, f, g, dm, dn, st);
-        rho_m = st.drho;
-        p_m = st.dp;
-        pull(y0, f, g);
-        row_state(y0, f, g, m_c, n_c, s_c);
-        pull(y0 + 1, f, g);
-        row_state(y0 + 1, f, g, m_n, n_n, s_n);
+        pull(yf - d, f, g);
+        row_state(yf - d, f, g, dm, dn, st);
+        rho_b = st.drho;
+        p_b = st.dp;
+        pull(yf, f, g);
+        row_state(yf, f, g, m_c, n_c, s_c);
+        pull(yf + d, f, g);
+        row_state(yf + d, f, g, m_n, n_n, s_n);
     }
 
-    for (int y = y0; y <= ylast; ++y) {
+    for (int i = 0; i < w.len; ++i) {
         if constexpr (Tuning<Fm>::lockstep) __syncthreads();
-        progress_priority(y - y0, w.len);
-        // loads of row y + 2 (on the last row a repeat of row y + 1, which
-        // is in cache and whose state is not used) before the collision
-        const int ynext = y < ylast ? y + 2 : y + 1;
+        progress_priority(i, w.len);
+        const int y = yf + i * d;
+        // loads of the row two ahead (on the last row a repeat of the row
+        // ahead, which is in cache and whose state is not used) before the
+        // collision
+        const int ynext = i + 1 < w.len ? y + 2 * d : y + d;
         C fr[9], gr[9];
         pull(ynext, fr, gr);
 
         // isotropic gradients d_a phi = 3 sum_q w_q e_qa phi(x + e_q), taken on
-        // the deviations rho - rho0 and p - p0
+        // the deviations rho - rho0 and p - p0, written symmetric in ahead /
+        // behind so that both march directions round alike
         const C rW = from_left(s_c.drho), rE = from_right(s_c.drho);
-        const C rSW = from_left(rho_m), rSE = from_right(rho_m);
-        const C rNW = from_left(s_n.drho), rNE = from_right(s_n.drho);
+        const C rBW = from_left(rho_b), rBE = from_right(rho_b);
+        const C rAW = from_left(s_n.drho), rAE = from_right(s_n.drho);
         const C pW = from_left(s_c.dp), pE = from_right(s_c.dp);
-        const C pSW = from_left(p_m), pSE = from_right(p_m);
-        const C pNW = from_left(s_n.dp), pNE = from_right(s_n.dp);
-        const C gr_x = (rE - rW) * C(1.0 / 3.0) + (rNE + rSE - rNW - rSW) * C(1.0 / 12.0);
-        const C gr_y = (s_n.drho - rho_m) * C(1.0 / 3.0) + (rNE + rNW - rSE - rSW) * C(1.0 / 12.0);
-        const C gp_x = (pE - pW) * C(1.0 / 3.0) + (pNE + pSE - pNW - pSW) * C(1.0 / 12.0);
-        const C gp_y = (s_n.dp - p_m) * C(1.0 / 3.0) + (pNE + pNW - pSE - pSW) * C(1.0 / 12.0);
+        const C pBW = from_left(p_b), pBE = from_right(p_b);
+        const C pAW = from_left(s_n.dp), pAE = from_right(s_n.dp);
+        const C fd = C(d);
+        const C gr_x = (rE - rW) * C(1.0 / 3.0) + ((rAE - rAW) + (rBE - rBW)) * C(1.0 / 12.0);
+        const C gr_y = fd * ((s_n.drho - rho_b) * C(1.0 / 3.0) + ((rAE + rAW) - (rBE + rBW)) * C(1.0 / 12.0));
+        const C gp_x = (pE - pW) * C(1.0 / 3.0) + ((pAE - pAW) + (pBE - pBW)) * C(1.0 / 12.0);
+        const C gp_y = fd * ((s_n.dp - p_b) * C(1.0 / 3.0) + ((pAE + pAW) - (pBE + pBW)) * C(1.0 / 12.0));
 
         C fb[9], gb[9];
         collide_interior<C>(P, K, s_c, m_c, n_c, gr_x, gr_y, gp_x, gp_y, fb, gb);
@@ -507,8 +518,8 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
             Store<G>::bstore(ro, vg_out, g_base + q * grow_bytes, gb[q]);
         }
         if (EXPORT && out_lane) export_node<C>(P, c, y, s_c, K.T0_d + double(s_c.dT));
-        rho_m = s_c.drho;
-        p_m = s_c.dp;
+        rho_b = s_c.drho;
+        p_b = s_c.dp;
         s_c = s_n;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -728,7 +739,7 @@ __attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
     w.x0 = wk->x0;
     w.y0 = wk->y0;
     w.len = wk->len;
-    w.pad = 0;
+    w.dir = wk->dir;
     if (w.kind == 2) return;
     progress_priority(0, 1);
     const CaseParams& P = *(const CaseParams*)(((const __attribute__((address_space(4))) CaseParams*)cases) + w.case_id);

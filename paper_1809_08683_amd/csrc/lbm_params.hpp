@@ -52,10 +52,10 @@ struct CaseParams {
 
 // One wavefront's share of a step.
 //   kind 0: interior strip, output columns [x0, x0 + 60) clipped to the off-wall
-//           range, rows [y0, y0 + len)
+//           range, rows [y0, y0 + len), marched upwards (dir 0) or downwards (dir 1)
 //   kind 1: wall nodes [x0, x0 + len) of the case's wall-node enumeration
 struct WorkItem {
-    int case_id, kind, x0, y0, len, pad;
+    int case_id, kind, x0, y0, len, dir;
 };
 
 }  // namespace lbm
