@@ -18,6 +18,8 @@ int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int
                 int export_macros, hipStream_t stream);
 int step_blocks_per_cu(int prec);
 int step_lockstep(int prec);
+int step_xwall_in_strips(int prec);
+double step_xwall_cost(int prec);
 int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
                 int parity, hipStream_t stream);
 int launch_totals(const CaseParams* d_cases, int case_id, double* d_partial, int nblocks, double* d_out,
@@ -245,15 +247,16 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
 // Work decomposition of one step.  The off-wall region of every case is cut
 // into strips of 60 columns and each strip into segments of nearly equal
 // height; by default the number of segments is chosen so that all items of
-// a step are resident at once (one round of wavefronts).  Wall nodes are
-// split over wavefronts in proportion to their cost, at least one per CU
-// (each wavefront takes its nodes 64 at a time).  Without
+// a step are resident at once (one round of wavefronts).  Where the format
+// allows it, the strips next to an x-wall also collide its nodes (with
+// shorter segments, as their rows cost more); the other wall nodes go to
+// wall items, split over wavefronts in proportion to their cost.  Without
 // lockstep every wall wavefront goes to a block of its own, so that each CU
 // carries the same mix of wall and interior work; with lockstep the wall
 // wavefronts fill blocks of their own.  Block b runs on XCD b % 8; the
 // interior items of one contiguous band of rows go to the blocks of one XCD,
 // four neighbouring strips of a segment per block.
-bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, bool lockstep)
+bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, bool lockstep, bool xw_strips, double xw_cost)
 {
     constexpr int NX = 8;
     constexpr int PB = 4;   // wavefronts per block
@@ -265,50 +268,85 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, bool locks
     for (int k = 0; k < nc; ++k) {
         const auto& P = c->P[k];
         if (P.wall_y) nwall[k] += 2 * P.nx;
-        if (P.wall_x) nwall[k] += 2 * (P.wall_y ? P.ny - 2 : P.ny);
+        if (P.wall_x && !xw_strips) nwall[k] += 2 * (P.wall_y ? P.ny - 2 : P.ny);
         total_wall += nwall[k];
         const int xr = P.wall_x ? P.nx - 2 : P.nx, yr = P.wall_y ? P.ny - 2 : P.ny;
         total_cells += (long long)((xr + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS) * yr;
     }
-    std::vector<lbm::WorkItem> wall, inner;
+    std::vector<lbm::WorkItem> wall;
     if (total_wall > 0) {
         // Wall wavefronts get the share of the slots that their work needs:
         // a wall node costs about kWallCost interior nodes (its own pull, the
-        // pulls at x_f, x_ff and of its gradient neighbours, the inversions).
-        // At least one per CU while that leaves 16 or more nodes to each;
-        // a wavefront takes its nodes 64 at a time.
+        // pulls at x_f, x_ff along the inner normal and of its gradient
+        // neighbours, the inversions).  A wavefront takes its nodes 64 at a
+        // time: chunks of wall rows are whole multiples of 64.  The nodes of
+        // x-wall columns (one cache line per node and DF row) are spread
+        // over at least one wavefront per CU while that leaves 16 or more
+        // nodes to each.
         constexpr double kWallCost = 12.0;
         const double interior = double(total_cells) * lbm::STRIP_COLS;
         const double frac = kWallCost * double(total_wall) / (kWallCost * double(total_wall) + interior);
-        long long nw = (long long)std::llround(frac * double(capacity));
-        nw = std::max(nw, std::min<long long>(cus, (total_wall + 15) / 16));
-        nw = std::max<long long>(nw, 1);
-        const int chunk = int((total_wall + nw - 1) / nw);
+        long long nw = std::max<long long>((long long)std::llround(frac * double(capacity)), 1);
+        bool columns = false;
+        for (int k = 0; k < nc; ++k) columns = columns || (c->P[k].wall_x && !xw_strips);
+        int chunk;
+        if (columns) {
+            nw = std::max(nw, std::min<long long>(cus, (total_wall + 15) / 16));
+            chunk = int((total_wall + nw - 1) / nw);
+        } else {
+            const long long per = (total_wall + nw - 1) / nw;
+            chunk = int((per + lbm::REGION_SLOTS - 1) / lbm::REGION_SLOTS * lbm::REGION_SLOTS);   // 64 lanes
+        }
         for (int k = 0; k < nc; ++k)
             for (int b = 0; b < nwall[k]; b += chunk) wall.push_back({k, 1, b, 0, std::min(chunk, nwall[k] - b), 0});
     }
     const long long budget = std::max<long long>(capacity - (long long)wall.size(), 1);
+    // Interior items in (case, first row, strip) order; the edge strips of a
+    // walled-x case (first and last) also collide the x-wall nodes, so a row
+    // of theirs costs xw_cost plain rows: by default they get that many
+    // times more (shorter) segments.
+    struct Cand {
+        lbm::WorkItem w;
+        double cost;
+        bool edge;
+    };
+    std::vector<Cand> items;
+    double strip_rows = 0.0;   // cost-weighted strip-rows over all cases
     for (int k = 0; k < nc; ++k) {
         const auto& P = c->P[k];
-        const int xlo = P.wall_x, xhi = P.wall_x ? P.nx - 1 : P.nx;
-        const int ylo = P.wall_y, yhi = P.wall_y ? P.ny - 1 : P.ny;
-        const int rows = yhi - ylo, strips = (xhi - xlo + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS;
-        int nseg;
+        const int strips = P.nstrips, rows = P.wall_y ? P.ny - 2 : P.ny;
+        const int nedge = P.wall_x && xw_strips ? std::min(strips, 2) : 0;
+        strip_rows += (double(strips - nedge) + xw_cost * nedge) * rows;
+    }
+    for (int k = 0; k < nc; ++k) {
+        const auto& P = c->P[k];
+        const int xlo = P.wall_x, ylo = P.wall_y;
+        const int rows = P.wall_y ? P.ny - 2 : P.ny, strips = P.nstrips;
+        auto is_edge = [&](int st) { return xw_strips && P.wall_x && (st == 0 || st == strips - 1); };
+        int nseg, nseg_e;
         if (seg_rows > 0) {
-            nseg = (rows + seg_rows - 1) / seg_rows;
+            nseg = nseg_e = (rows + seg_rows - 1) / seg_rows;
         } else {
             // this case's share of the resident slots, segments of >= 4 rows
-            const double share = double(strips) * rows / double(total_cells) * double(budget);
-            nseg = int(std::max(1.0, std::floor(share / strips)));
+            nseg = int(std::max(1.0, std::floor(double(budget) * rows / strip_rows)));
             nseg = std::min(nseg, std::max(1, rows / 4));
+            nseg_e = std::min(std::max(1, int(std::lround(xw_cost * nseg))), std::max(1, rows / 2));
         }
-        for (int g = 0; g < nseg; ++g) {
-            const int y0 = ylo + int((long long)rows * g / nseg);
-            const int y1 = ylo + int((long long)rows * (g + 1) / nseg);
-            if (y1 <= y0) continue;
-            for (int st = 0; st < strips; ++st)
-                inner.push_back({k, 0, xlo + lbm::STRIP_COLS * st, y0, y1 - y0, g & 1});
+        const size_t first = items.size();
+        for (int st = 0; st < strips; ++st) {
+            const bool e = is_edge(st);
+            const int n = e ? nseg_e : nseg;
+            for (int g = 0; g < n; ++g) {
+                const int y0 = ylo + int((long long)rows * g / n);
+                const int y1 = ylo + int((long long)rows * (g + 1) / n);
+                if (y1 <= y0) continue;
+                items.push_back({{k, 0, xlo + lbm::STRIP_COLS * st, y0, y1 - y0, g & 1},
+                                 double(y1 - y0) * (e ? xw_cost : 1.0), e});
+            }
         }
+        std::stable_sort(items.begin() + first, items.end(), [](const Cand& a, const Cand& b) {
+            return a.w.y0 != b.w.y0 ? a.w.y0 < b.w.y0 : a.w.x0 < b.w.x0;
+        });
     }
     // Wall item i goes to slot i / nblocks of block i % nblocks (one per block
     // first, spreading them over the CUs).  When interior waves march in
@@ -327,22 +365,44 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, bool locks
         for (auto& u : used)
             if (u > 0) u = PB;
     const long long wall_blocks = (long long)used.size();
-    // interior band k (a contiguous run of the item list) fills the free
-    // slots of blocks k, k + 8, ... in order; blocks past the resident count
-    // are added if a band needs them
+    // Band k (the items whose cost midpoint lies in the k-th eighth of the
+    // total, a contiguous run of rows) fills the free slots of blocks k,
+    // k + 8, ... of XCD k; with lockstep its edge items first fill blocks of
+    // their own, as their rows take longer.  Blocks past the resident count
+    // are added if a band needs them.
+    double total_cost = 0.0;
+    for (const auto& it : items) total_cost += it.cost;
+    std::vector<std::vector<size_t>> band(NX);
+    {
+        double acc = 0.0;
+        for (size_t i = 0; i < items.size(); ++i) {
+            const double mid = acc + 0.5 * items[i].cost;
+            acc += items[i].cost;
+            const int k = std::min(NX - 1, int(mid / std::max(total_cost, 1e-300) * NX));
+            band[size_t(k)].push_back(i);
+        }
+    }
     long long total_blocks = (long long)round_up(size_t(wall_blocks), NX);
     for (int k = 0; k < NX; ++k) {
-        const size_t lo = inner.size() * k / NX, hi = inner.size() * (k + 1) / NX;
         long long blk = k;
         int fill = blk < wall_blocks ? used[size_t(blk)] : 0;
-        for (size_t i = lo; i < hi; ++i) {
+        auto put = [&](const lbm::WorkItem& w) {
             while (fill >= PB) {
                 blk += NX;
                 fill = blk < wall_blocks ? used[size_t(blk)] : 0;
             }
-            placed.push_back({blk * PB + fill, inner[i]});
+            placed.push_back({blk * PB + fill, w});
             ++fill;
             total_blocks = std::max(total_blocks, (blk / NX + 1) * NX);
+        };
+        if (lockstep) {
+            for (size_t i : band[size_t(k)])
+                if (items[i].edge) put(items[i].w);
+            if (fill > 0) fill = PB;   // blocks of edge items hold nothing else
+            for (size_t i : band[size_t(k)])
+                if (!items[i].edge) put(items[i].w);
+        } else {
+            for (size_t i : band[size_t(k)]) put(items[i].w);
         }
     }
     c->work.assign(size_t(total_blocks * PB), lbm::WorkItem{0, 2, 0, 0, 0, 0});
@@ -350,7 +410,7 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, bool locks
         if (pr.first < 0 || pr.first >= (long long)c->work.size() || c->work[size_t(pr.first)].kind != 2) return false;
         c->work[size_t(pr.first)] = pr.second;
     }
-    c->n_items = (long long)(wall.size() + inner.size());
+    c->n_items = (long long)(wall.size() + items.size());
     return true;
 }
 
@@ -409,7 +469,8 @@ lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* 
     }
     int cus = 0;
     HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
-    if (!build_work(c, opt[0].seg_rows, cus, lbm::step_blocks_per_cu(c->prec), lbm::step_lockstep(c->prec) != 0))
+    if (!build_work(c, opt[0].seg_rows, cus, lbm::step_blocks_per_cu(c->prec), lbm::step_lockstep(c->prec) != 0,
+                    lbm::step_xwall_in_strips(c->prec) != 0, lbm::step_xwall_cost(c->prec)))
         return fail(c, LBM_EDEVICE, "internal error: inconsistent work list");
     void* p = nullptr;
     HIP_TRY(c, hipMalloc(&p, sizeof(lbm::CaseParams) * ncases));

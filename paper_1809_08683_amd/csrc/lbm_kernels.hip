@@ -55,23 +55,35 @@ using FmtF32G16 = Format<float, __half>;
 // strips read the lines their neighbours fetch at the same moment); whether
 // the strips next to an x-wall select the wall state of their wall lanes
 // instead of branching (needs a few more registers); whether segments of a
-// band alternate their march direction (the 16-bit format spills with it).
+// band alternate their march direction (the 16-bit format spills with it);
+// whether the strips next to an x-wall collide its nodes (else wall items
+// take them; FP64 has no registers to spare for it), the time of a row of
+// such a strip relative to a plain row, and whether it loads the row two
+// ahead before the collision (where the registers allow it).
 template <typename Fm> struct Tuning;
 template <> struct Tuning<FmtF64> {
     static constexpr int waves = 2;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
+    static constexpr bool xw_strips = false, xw_prefetch = false;
+    static constexpr double xw_cost = 1.0;
 };
 template <> struct Tuning<FmtF32> {
     static constexpr int waves = 3;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
+    static constexpr bool xw_strips = true, xw_prefetch = true;
+    static constexpr double xw_cost = 1.65;
 };
 template <> struct Tuning<FmtF32G16> {
     static constexpr int waves = 3;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
+    static constexpr bool xw_strips = true, xw_prefetch = true;
+    static constexpr double xw_cost = 1.45;
 };
 template <> struct Tuning<FmtF16> {
     static constexpr int waves = 4;
     static constexpr bool lockstep = false, edge_select = false, alternate = false;
+    static constexpr bool xw_strips = true, xw_prefetch = false;
+    static constexpr double xw_cost = 2.0;
 };
 static_assert(REGION_SLOTS == WAVE && STRIP_COLS == WAVE - 4, "one wavefront per strip region");
 
@@ -275,17 +287,76 @@ __device__ __forceinline__ void export_node(const CaseParams& P, int x, int y, c
 //   App. C step 4), conserved row nbar_0 = n_0 + q_e.
 // The f and g post-collision deviations go to fb and gb.
 // ---------------------------------------------------------------------------
+// Whole-wavefront lane shifts by one lane (DPP wave_shr:1 / wave_shl:1):
+// lane l receives the value of lane l - 1 (from_left) or l + 1 (from_right);
+// lane 0, resp. 63, receives 0.  Every lane of the wavefront must be active.
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+template <int CTRL>
+__device__ __forceinline__ int dpp_shift(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float v)
+{
+    return __int_as_float(dpp_shift<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = unsigned(dpp_shift<CTRL>(int(unsigned(u)))), hi = unsigned(dpp_shift<CTRL>(int(unsigned(u >> 32))));
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
 template <typename C>
+__device__ __forceinline__ C from_left(C v) { return dpp_shift<kDppWaveShr1>(v); }
+template <typename C>
+__device__ __forceinline__ C from_right(C v) { return dpp_shift<kDppWaveShl1>(v); }
+
+// Lanes of a strip that holds an x-wall column collide the wall node there
+// (Sec. 3.1): its non-equilibrium part is not its own but the tilde moments
+// of the off-wall nodes x_f = x_w + n and x_ff = x_w + 2n along the inner
+// normal n, extrapolated to first or second order (eq. neq.extrapolation,
+// Zm = Ntil(x_f) [2 Ntil(x_f) - Ntil(x_ff)], Zn likewise from
+// Htil + (Y/2) Ntil), and inverted with the wall node's own S, L and Y
+// (App. B).  x_f and x_ff are collided by the neighbouring lanes of the same
+// row, whose tilde moments are read by lane permutation.
+struct XWallLane {
+    bool wall;       // this lane collides a wall node
+    bool left;       // ... of the left wall (x_f, x_ff on the lanes above it; else below)
+    bool order2;     // second-order extrapolation
+};
+
+template <typename C>
+__device__ __forceinline__ C lane_extrap(C v, const XWallLane& xl)
+{
+    // both directions are shifted by every lane before a lane selects one
+    const C r1 = from_right(v), l1 = from_left(v);
+    const C a = xl.left ? r1 : l1;
+    if (!xl.order2) return a;
+    const C r2 = from_right(r1), l2 = from_left(l1);
+    return C(2) * a - (xl.left ? r2 : l2);
+}
+
+// With XW, the wall lanes of the row take the extrapolated pair: with
+// Ntil := Zm, N := (I - S/2)^-1 Zm, Htil := Zn - (Y/2) Zm, H := (I - L/2)^-1 Htil
+// and m := m^eq - F_m/2 + N, n := n^eq - Q_m/2 + H substituted, the update
+// below is the post-collision state of the wall node.  The lanes of x_f and
+// x_ff are off-wall lanes, so their Ntil and Htil are their own when the
+// wall lanes read them.
+template <typename C, bool XW = false>
 __device__ __forceinline__ void collide_interior(const CaseParams& P, const Coef<C>& K, const NodeState<C>& s,
                                                  const C m[9], const C n[9],
-                                                 C gr_x, C gr_y, C gp_x, C gp_y, C fb[9], C gb[9])
+                                                 C gr_x, C gr_y, C gp_x, C gp_y, C fb[9], C gb[9],
+                                                 const XWallLane& xl = XWallLane{false, false, false})
 {
     Rates<C> r;
     local_rates<C>(K, P.visc_law, s, r);
     const Forcing<C> F = forcing<C>(K, P.per_mass, s);
     C G1, G7, G8;
+    C y3 = C(0), y5 = C(0);   // (Y/2)-part of Htil from this lane's u and Ntil (XW)
     {
-        C meq[9], N[9], Nt[9], mb[9];
+        C meq[9], N[9], Nt[9], mb[9], mm[9];
         {
             C Fm[9];
             meq_f<C>(s, meq);
@@ -295,15 +366,34 @@ __device__ __forceinline__ void collide_interior(const CaseParams& P, const Coef
             N[0] = C(0);
             N[3] = C(0);
             N[5] = C(0);
+            tilde_f<C>(s, r, N, Nt);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) mm[i] = m[i];
+            if constexpr (XW) {
+                // every lane takes part in the permutations (a lane reading
+                // from a lane switched off by a branch would read nothing)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    if (i == 0 || i == 3 || i == 5) continue;
+                    const C z = lane_extrap<C>(Nt[i], xl);
+                    Nt[i] = xl.wall ? z : Nt[i];
+                }
+                untilde_f<C>(s, r, Nt, N);
+                C Fw[9];
+                force_moments<C>(s, F, Fw);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) mm[i] = xl.wall ? meq[i] - C(0.5) * Fw[i] + N[i] : m[i];
+                y3 = s.ux * (C(1.0 / 3.0) * Nt[1] + Nt[7]) + C(2) * s.uy * Nt[8];
+                y5 = s.uy * (C(1.0 / 3.0) * Nt[1] - Nt[7]) + C(2) * s.ux * Nt[8];
+            }
         }
-        tilde_f<C>(s, r, N, Nt);
         C c1, c7, c8;
         corrections<C>(s, r, P.cubic, Nt, gr_x, gr_y, gp_x, gp_y, c1, c7, c8);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) mb[i] = C(2) * meq[i] - m[i] + C(2) * Nt[i];
-        mb[0] = m[0];
-        mb[3] = m[3] + F.Fx;
-        mb[5] = m[5] + F.Fy;
+        for (int i = 0; i < 9; ++i) mb[i] = C(2) * meq[i] - mm[i] + C(2) * Nt[i];
+        mb[0] = mm[0];
+        mb[3] = mm[3] + F.Fx;
+        mb[5] = mm[5] + F.Fy;
         mb[1] -= c1;
         mb[7] -= c7;
         mb[8] -= c8;
@@ -314,7 +404,7 @@ __device__ __forceinline__ void collide_interior(const CaseParams& P, const Coef
         from_moments<C>(mb, fb);
     }
     {
-        C neq[9], Hm[9], Ht[9], nb[9];
+        C neq[9], Hm[9], Ht[9], nb[9], nn[9];
         {
             C Qm[9];
             neq_g<C>(K, s, neq);
@@ -322,17 +412,36 @@ __device__ __forceinline__ void collide_interior(const CaseParams& P, const Coef
 #pragma unroll
             for (int i = 0; i < 9; ++i) Hm[i] = n[i] - neq[i] + C(0.5) * Qm[i];
             Hm[0] = C(0);
-        }
-        tilde_g<C>(r, Hm, Ht);
+            tilde_g<C>(r, Hm, Ht);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) nb[i] = C(2) * neq[i] - n[i] + C(2) * Ht[i];
-        nb[0] = n[0] + F.qe;
-        const C y3 = s.ux * (C(1.0 / 3.0) * G1 + G7) + C(2) * s.uy * G8;
-        const C y5 = s.uy * (C(1.0 / 3.0) * G1 - G7) + C(2) * s.ux * G8;
-        nb[3] += y3;
-        nb[4] -= y3;
-        nb[5] += y5;
-        nb[6] -= y5;
+            for (int i = 0; i < 9; ++i) nn[i] = n[i];
+            if constexpr (XW) {
+                // Zn = Htil + (Y/2) Ntil of the off-wall lanes, extrapolated;
+                // the wall's Htil = Zn - (Y/2) Zm with the wall velocity
+#pragma unroll
+                for (int i = 1; i < 9; ++i) {
+                    const C ys = i == 3 || i == 4 ? y3 : (i == 5 || i == 6 ? y5 : C(0));
+                    const C sgn = i == 3 || i == 5 ? C(0.5) : C(-0.5);
+                    const C zo = (i >= 3 && i <= 6) ? Ht[i] + sgn * ys : Ht[i];
+                    const C zw = lane_extrap<C>(zo, xl);
+                    Ht[i] = xl.wall ? ((i >= 3 && i <= 6) ? zw - sgn * ys : zw) : Ht[i];
+                }
+                untilde_g<C>(r, Ht, Hm);
+                C Qw[9];
+                source_moments<C>(s, F, Qw);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) nn[i] = xl.wall ? neq[i] - C(0.5) * Qw[i] + Hm[i] : n[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) nb[i] = C(2) * neq[i] - nn[i] + C(2) * Ht[i];
+        nb[0] = nn[0] + F.qe;
+        const C z3 = s.ux * (C(1.0 / 3.0) * G1 + G7) + C(2) * s.uy * G8;
+        const C z5 = s.uy * (C(1.0 / 3.0) * G1 - G7) + C(2) * s.ux * G8;
+        nb[3] += z3;
+        nb[4] -= z3;
+        nb[5] += z5;
+        nb[6] -= z5;
         from_moments<C>(nb, gb);
     }
 }
@@ -357,11 +466,6 @@ __device__ __forceinline__ void progress_priority(int done, int total)
     }
 }
 
-template <typename C>
-__device__ __forceinline__ C from_left(C v) { return __shfl_up(v, 1, WAVE); }
-template <typename C>
-__device__ __forceinline__ C from_right(C v) { return __shfl_down(v, 1, WAVE); }
-
 // stored row (0 .. ny+1) of lattice row v in [-1, ny], wrapped on a periodic axis
 __device__ __forceinline__ int stored_row(int v, int n, int walled)
 {
@@ -384,7 +488,7 @@ __device__ __forceinline__ int stored_row(int v, int n, int walled)
 // be written get an offset past the record count, which the hardware drops,
 // so the loads of row y + 2 stay in flight across the collision and the
 // stores of row y.
-template <typename Fm, bool EXPORT>
+template <typename Fm, bool EXPORT, bool XW>
 __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkItem w, const char* __restrict__ src_in,
                                               char* __restrict__ dst_in)
 {
@@ -419,7 +523,16 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     const int vf0 = sl0 * EF, vf1 = sl1 * EF, vf2 = sl2 * EF;
     const int vg0 = sl0 * EG, vg1 = sl1 * EG, vg2 = sl2 * EG;
     // slots this lane stores: all but the wall and ghost slots of a walled side
-    const bool keep = wall_x && (c == -1 || c == 0 || c == nx - 1 || c == nx);
+    // x-wall nodes collided by this strip (XW: the case has them in its
+    // strips and this strip holds the column 0 or nx - 1 on a lane 1..62)
+    XWallLane xl{false, false, P.extrap_order == 2};
+    if constexpr (XW) {
+        xl.left = c == 0;
+        xl.wall = lane >= 1 && lane <= REGION_SLOTS - 2 && (c == 0 || c == nx - 1);
+    }
+    // the strip holds the left / right wall column (wave-uniform)
+    const bool has_left = XW && X == P.xlo, has_right = XW && X + STRIP_COLS >= nx - 1;
+    const bool keep = wall_x && (c == -1 || c == 0 || c == nx - 1 || c == nx) && !xl.wall;
     const int vf_out = keep ? kDropOffset : (region + lane) * EF;
     const int vg_out = keep ? kDropOffset : (region + lane) * EG;
     const bool out_lane = lane >= 2 && lane < 2 + STRIP_COLS && c < xhi;   // own nodes
@@ -492,7 +605,7 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
         // collision
         const int ynext = i + 1 < w.len ? y + 2 * d : y + d;
         C fr[9], gr[9];
-        pull(ynext, fr, gr);
+        if constexpr (!XW || Tuning<Fm>::xw_prefetch) pull(ynext, fr, gr);
 
         // isotropic gradients d_a phi = 3 sum_q w_q e_qa phi(x + e_q), taken on
         // the deviations rho - rho0 and p - p0, written symmetric in ahead /
@@ -510,14 +623,57 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
         const C gp_y = fd * ((s_n.dp - p_b) * C(1.0 / 3.0) + ((pAE + pAW) - (pBE + pBW)) * C(1.0 / 12.0));
 
         C fb[9], gb[9];
-        collide_interior<C>(P, K, s_c, m_c, n_c, gr_x, gr_y, gp_x, gp_y, fb, gb);
+        if constexpr (XW) {
+            // gradients at a wall node: second-order one-sided along x from
+            // x_f and x_ff, two-point central along y
+            const C r1 = xl.left ? rE : rW, p1 = xl.left ? pE : pW;
+            const C rEE = from_right(rE), rWW = from_left(rW), pEE = from_right(pE), pWW = from_left(pW);
+            const C r2 = xl.left ? rEE : rWW, p2 = xl.left ? pEE : pWW;
+            const C sg = xl.left ? C(1) : C(-1);
+            const C wr_x = sg * ((C(-3) * s_c.drho + C(4) * r1 - r2) * C(0.5));
+            const C wp_x = sg * ((C(-3) * s_c.dp + C(4) * p1 - p2) * C(0.5));
+            const C wr_y = fd * ((s_n.drho - rho_b) * C(0.5));
+            const C wp_y = fd * ((s_n.dp - p_b) * C(0.5));
+            collide_interior<C, true>(P, K, s_c, m_c, n_c, xl.wall ? wr_x : gr_x, xl.wall ? wr_y : gr_y,
+                                      xl.wall ? wp_x : gp_x, xl.wall ? wp_y : gp_y, fb, gb, xl);
+        } else {
+            collide_interior<C>(P, K, s_c, m_c, n_c, gr_x, gr_y, gp_x, gp_y, fb, gb);
+        }
         const rsrc_t ro = make_rsrc(dst + (long long)(y + 1) * blk, blk_bytes);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             Store<F>::bstore(ro, vf_out, q * frow_bytes, fb[q]);
             Store<G>::bstore(ro, vg_out, g_base + q * grow_bytes, gb[q]);
         }
-        if (EXPORT && out_lane) export_node<C>(P, c, y, s_c, K.T0_d + double(s_c.dT));
+        if constexpr (XW) {
+            // the DFs a wall node sends out of the domain go to the ghost
+            // column next to it, in the row they reach and as the opposite
+            // direction (the bounce-back of the next pull)
+            const rsrc_t rp = make_rsrc(dst + (long long)stored_row(y + 1, ny, wall_y) * blk, blk_bytes);
+            const rsrc_t rm = make_rsrc(dst + (long long)stored_row(y - 1, ny, wall_y) * blk, blk_bytes);
+            const int gsl = region + (xl.left ? lane - 1 : lane + 1);
+            if (has_left) {
+                // left wall: q = 3, 6, 7 leave as 1, 8, 5 in rows y, y + 1, y - 1
+                const int vf = xl.wall && xl.left ? gsl * EF : kDropOffset, vg = xl.wall && xl.left ? gsl * EG : kDropOffset;
+                Store<F>::bstore(ro, vf, 1 * frow_bytes, fb[3]);
+                Store<G>::bstore(ro, vg, g_base + 1 * grow_bytes, gb[3]);
+                Store<F>::bstore(rp, vf, 8 * frow_bytes, fb[6]);
+                Store<G>::bstore(rp, vg, g_base + 8 * grow_bytes, gb[6]);
+                Store<F>::bstore(rm, vf, 5 * frow_bytes, fb[7]);
+                Store<G>::bstore(rm, vg, g_base + 5 * grow_bytes, gb[7]);
+            }
+            if (has_right) {
+                // right wall: q = 1, 5, 8 leave as 3, 7, 6 in rows y, y + 1, y - 1
+                const int vf = xl.wall && !xl.left ? gsl * EF : kDropOffset, vg = xl.wall && !xl.left ? gsl * EG : kDropOffset;
+                Store<F>::bstore(ro, vf, 3 * frow_bytes, fb[1]);
+                Store<G>::bstore(ro, vg, g_base + 3 * grow_bytes, gb[1]);
+                Store<F>::bstore(rp, vf, 7 * frow_bytes, fb[5]);
+                Store<G>::bstore(rp, vg, g_base + 7 * grow_bytes, gb[5]);
+                Store<F>::bstore(rm, vf, 6 * frow_bytes, fb[8]);
+                Store<G>::bstore(rm, vg, g_base + 6 * grow_bytes, gb[8]);
+            }
+        }
+        if (EXPORT && (out_lane || xl.wall)) export_node<C>(P, c, y, s_c, K.T0_d + double(s_c.dT));
         rho_b = s_c.drho;
         p_b = s_c.dp;
         s_c = s_n;
@@ -526,6 +682,7 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
             m_c[q] = m_n[q];
             n_c[q] = n_n[q];
         }
+        if constexpr (XW && !Tuning<Fm>::xw_prefetch) pull(ynext, fr, gr);
         row_state(ynext, fr, gr, m_n, n_n, s_n);
     }
 }
@@ -533,16 +690,9 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
 // ---------------------------------------------------------------------------
 // wall item
 // ---------------------------------------------------------------------------
-// Wall nodes of a case, enumerated as: bottom row, top row (walled y), then
-// left and right columns without the corners (walled x).
-__device__ __forceinline__ int wall_node_count(const CaseParams& P)
-{
-    int n = 0;
-    if (P.wall_y) n += 2 * P.nx;
-    if (P.wall_x) n += 2 * (P.wall_y ? P.ny - 2 : P.ny);
-    return n;
-}
-
+// Wall nodes a case gives to wall items, enumerated as: bottom row, top row
+// (walled y, corners included), then, when the strips next to the x-walls
+// do not collide them, the left and right columns between those rows.
 __device__ __forceinline__ void wall_node_xy(const CaseParams& P, int i, int& x, int& y)
 {
     if (P.wall_y) {
@@ -552,10 +702,8 @@ __device__ __forceinline__ void wall_node_xy(const CaseParams& P, int i, int& x,
         i -= P.nx;
     }
     const int ylo = P.wall_y ? 1 : 0, len = P.wall_y ? P.ny - 2 : P.ny;
-    if (i < len) { x = 0; y = ylo + i; return; }
-    i -= len;
-    x = P.nx - 1;
-    y = ylo + i;
+    x = i < len ? 0 : P.nx - 1;
+    y = ylo + (i < len ? i : i - len);
 }
 
 template <typename Fm>
@@ -743,8 +891,19 @@ __attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
     if (w.kind == 2) return;
     progress_priority(0, 1);
     const CaseParams& P = *(const CaseParams*)(((const __attribute__((address_space(4))) CaseParams*)cases) + w.case_id);
-    if (w.kind == 0)
-        interior_item<Fm, EXPORT>(P, w, static_cast<const char*>(P.buf[parity]), static_cast<char*>(P.buf[parity ^ 1]));
+    if (w.kind == 0) {
+        const char* src = static_cast<const char*>(P.buf[parity]);
+        char* dst = static_cast<char*>(P.buf[parity ^ 1]);
+        bool xw = false;
+        if constexpr (Tuning<Fm>::xw_strips) xw = P.wall_x && (w.x0 == P.xlo || w.x0 + STRIP_COLS >= P.nx - 1);
+        if constexpr (Tuning<Fm>::xw_strips) {
+            if (xw) {
+                interior_item<Fm, EXPORT, true>(P, w, src, dst);
+                return;
+            }
+        }
+        interior_item<Fm, EXPORT, false>(P, w, src, dst);
+    }
     else
         wall_item<Fm, EXPORT>(P, w, static_cast<const char*>(P.buf[parity]), static_cast<char*>(P.buf[parity ^ 1]));
 }
@@ -1001,6 +1160,17 @@ int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int
 int step_lockstep(int prec)
 {
     return with_format(prec, [](auto fm) { return int(Tuning<decltype(fm)>::lockstep); });
+}
+
+// Whether the strips next to an x-wall collide its nodes, and the time of a
+// row of such a strip relative to a plain row.
+int step_xwall_in_strips(int prec)
+{
+    return with_format(prec, [](auto fm) { return int(Tuning<decltype(fm)>::xw_strips); });
+}
+double step_xwall_cost(int prec)
+{
+    return with_format(prec, [](auto fm) { return Tuning<decltype(fm)>::xw_cost; });
 }
 
 // Resident 256-thread blocks of the step kernel per CU for a precision.

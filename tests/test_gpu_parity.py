@@ -96,6 +96,16 @@ SMALL = {
     "cavity_ragged_strips_131x9": _cavity(131, ny=9),
     "cavity_ragged_segments_9x75": _cavity(9, ny=75),
     "wide_channel_150x20": inputs.poiseuille(nx=150, ny=20, nu=0.1, eos="ideal"),
+    # x-wall nodes collided by the edge strips: the narrowest case with
+    # second-order extrapolation, a right wall on lane 62 of the last strip,
+    # and a last strip of one column (the wall on lane 63 of the strip before
+    # it, which does not collide it)
+    "cavity_narrowest_5x9_order2": _cavity(5, ny=9, order=2),
+    "cavity_wall_lane62_122x7_order2": _cavity(122, ny=7, order=2),
+    "cavity_one_column_strip_123x7": _cavity(123, ny=7),
+    "vertical_channel_order2": inputs.base_case(nx=12, ny=10, nu0=0.1, force=(0, -1e-4), per_mass=True,
+                                                sides=[W(T=1.05, u=(0, 0.01)), W(T=0.95), P(), P()],
+                                                extrap_order=2),
 }
 
 
