@@ -19,6 +19,7 @@ int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int
 int step_blocks_per_cu(int prec);
 int step_lockstep(int prec);
 int step_xwall_in_strips(int prec);
+int step_block_waves(int prec);
 double step_xwall_cost(int prec);
 int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
                 int parity, hipStream_t stream);
@@ -255,11 +256,11 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
 // carries the same mix of wall and interior work; with lockstep the wall
 // wavefronts fill blocks of their own.  Block b runs on XCD b % 8; the
 // interior items of one contiguous band of rows go to the blocks of one XCD,
-// four neighbouring strips of a segment per block.
-bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, bool lockstep, bool xw_strips, double xw_cost)
+// neighbouring strips of a segment sharing a block.
+bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bool lockstep, bool xw_strips,
+                double xw_cost)
 {
     constexpr int NX = 8;
-    constexpr int PB = 4;   // wavefronts per block
     const int nc = int(c->P.size());
     const long long nblocks = (long long)round_up(size_t(std::max(cus, 1)) * size_t(std::max(blocks_per_cu, 1)), NX);
     const long long capacity = nblocks * PB;
@@ -469,7 +470,8 @@ lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* 
     }
     int cus = 0;
     HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
-    if (!build_work(c, opt[0].seg_rows, cus, lbm::step_blocks_per_cu(c->prec), lbm::step_lockstep(c->prec) != 0,
+    if (!build_work(c, opt[0].seg_rows, cus, lbm::step_blocks_per_cu(c->prec),
+                    lbm::step_block_waves(c->prec), lbm::step_lockstep(c->prec) != 0,
                     lbm::step_xwall_in_strips(c->prec) != 0, lbm::step_xwall_cost(c->prec)))
         return fail(c, LBM_EDEVICE, "internal error: inconsistent work list");
     void* p = nullptr;

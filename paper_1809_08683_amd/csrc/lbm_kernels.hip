@@ -32,7 +32,6 @@
 namespace lbm {
 
 constexpr int WAVE = 64;
-constexpr int WAVES_PER_BLOCK = 4;
 
 // Storage format of the DFs: element type of the nine f rows and of the
 // nine g rows of a stored row block (both decode to the arithmetic type C).
@@ -59,31 +58,36 @@ using FmtF32G16 = Format<float, __half>;
 // whether the strips next to an x-wall collide its nodes (else wall items
 // take them; FP64 has no registers to spare for it), the time of a row of
 // such a strip relative to a plain row, and whether it loads the row two
-// ahead before the collision (where the registers allow it).
+// ahead before the collision (where the registers allow it); the wavefronts
+// of a block (neighbouring strips of a segment share its CU).
 template <typename Fm> struct Tuning;
 template <> struct Tuning<FmtF64> {
+    static constexpr int block_waves = 8;
     static constexpr int waves = 2;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
     static constexpr bool xw_strips = false, xw_prefetch = false;
     static constexpr double xw_cost = 1.0;
 };
 template <> struct Tuning<FmtF32> {
+    static constexpr int block_waves = 4;
     static constexpr int waves = 3;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
     static constexpr bool xw_strips = true, xw_prefetch = true;
     static constexpr double xw_cost = 1.65;
 };
 template <> struct Tuning<FmtF32G16> {
+    static constexpr int block_waves = 4;
     static constexpr int waves = 3;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
     static constexpr bool xw_strips = true, xw_prefetch = true;
     static constexpr double xw_cost = 1.45;
 };
 template <> struct Tuning<FmtF16> {
+    static constexpr int block_waves = 8;
     static constexpr int waves = 4;
     static constexpr bool lockstep = false, edge_select = false, alternate = false;
     static constexpr bool xw_strips = true, xw_prefetch = false;
-    static constexpr double xw_cost = 2.0;
+    static constexpr double xw_cost = 3.0;
 };
 static_assert(REGION_SLOTS == WAVE && STRIP_COLS == WAVE - 4, "one wavefront per strip region");
 
@@ -863,7 +867,7 @@ __device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w,
 
 // ---------------------------------------------------------------------------
 // step kernel: one launch per time step.  The host lays the work list out
-// slot by slot (slot = block * WAVES_PER_BLOCK + wave) so that wall items
+// slot by slot (slot = block * Tuning::block_waves + wave) so that wall items
 // start first and each XCD's blocks cover one contiguous band of rows;
 // kind 2 marks an empty slot.
 // ---------------------------------------------------------------------------
@@ -871,11 +875,11 @@ __device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w,
 // EXPORT: also write the macros of the new time level and the divergence
 // flag (the last step of a call).
 template <typename Fm, bool EXPORT>
-__global__ __launch_bounds__(WAVE * WAVES_PER_BLOCK)
+__global__ __launch_bounds__(WAVE * Tuning<Fm>::block_waves)
 __attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
     const CaseParams* __restrict__ cases, const WorkItem* __restrict__ work, int nwork, int parity)
 {
-    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6));
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * Tuning<Fm>::block_waves + (threadIdx.x >> 6));
     if (wid >= nwork) return;
     // the case table and the work list are read-only during a step: reading
     // them through the constant address space keeps them in scalar loads and
@@ -1142,11 +1146,12 @@ int with_format(int prec, Fn&& fn)
 int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
                 int export_macros, hipStream_t stream)
 {
-    const dim3 block(WAVE * WAVES_PER_BLOCK);
-    const dim3 grid((nwork + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
     if (nwork == 0) return 0;
     return with_format(prec, [&](auto fm) {
         using Fm = decltype(fm);
+        constexpr int pb = Tuning<Fm>::block_waves;
+        const dim3 block(WAVE * pb);
+        const dim3 grid((nwork + pb - 1) / pb);
         if (export_macros)
             hipLaunchKernelGGL((step_kernel<Fm, true>), grid, block, 0, stream, d_cases, d_work, nwork, parity);
         else
@@ -1173,13 +1178,19 @@ double step_xwall_cost(int prec)
     return with_format(prec, [](auto fm) { return Tuning<decltype(fm)>::xw_cost; });
 }
 
-// Resident 256-thread blocks of the step kernel per CU for a precision.
+// Wavefronts per block of the step kernel.
+int step_block_waves(int prec)
+{
+    return with_format(prec, [](auto fm) { return Tuning<decltype(fm)>::block_waves; });
+}
+
+// Resident blocks of the step kernel per CU for a precision.
 int step_blocks_per_cu(int prec)
 {
     return with_format(prec, [](auto fm) {
         int n = 0;
         const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<decltype(fm), false>,
-                                                                          WAVE * WAVES_PER_BLOCK, 0);
+                                                                          WAVE * Tuning<decltype(fm)>::block_waves, 0);
         return e == hipSuccess ? n : 0;
     });
 }
