@@ -1,0 +1,138 @@
+"""The paper's channel validations (Secs. 4.1, 4.2) on the GPU path, at the
+paper's grid (64 columns, 64 lattice spacings across the channel):
+
+* parity with the FP64 oracle over the first steps of each configuration
+  and equation of state;
+* the steady profiles against the closed forms (eqs. Poiseuille.u.T,
+  Couette.u.T) and the densities against eq. rho.analytical, over the
+  paper's parameter ranges;
+* the two runs the paper reports as unstable for the ideal gas diverge,
+  while the other equations of state stay stable at the same parameters.
+
+The closed-form bars are the errors of this grid with a margin of about 2:
+second order in the grid for the Poiseuille profiles, and growing as Ma_e^2
+for the Couette profiles (the closed forms neglect compressibility).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_flows as pf
+from paper_1809_08683_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+NY, NX = 65, 64
+EOS = ["decoupled", "ideal", "cs"]
+
+
+def _steady(c, chunk=20000, cap=600000, tol=1e-9):
+    g = lbm.Context(c).init()
+    prev, n = None, 0
+    while n < cap:
+        g.step(chunk)
+        n += chunk
+        m = g.macros()
+        cur = np.concatenate([m["ux"][:, 0], m["T"][:, 0]])
+        if prev is not None and np.abs(cur - prev).max() < tol:
+            break
+        prev = cur
+    g.close()
+    assert np.abs(m["T"] - m["T"][:, :1]).max() < 1e-12, "profile not uniform in x"
+    return m, n
+
+
+def _parity(c, steps=200):
+    g = lbm.Context(c).init()
+    g.step(steps)
+    o = oracle.Oracle(c).init()
+    o.step(steps)
+    mg, mo = g.macros(), o.macros()
+    g.close()
+    scale_u = max(np.abs(mo["ux"]).max(), 1e-300)
+    for k in ("rho", "T", "p"):
+        assert np.abs(mg[k] - mo[k]).max() / np.abs(mo[k]).max() < 1e-10, k
+    for k in ("ux", "uy"):
+        assert np.abs(mg[k] - mo[k]).max() / scale_u < 1e-10, k
+
+
+@pytest.mark.parametrize("eos", EOS)
+def test_poiseuille_parity_with_oracle(eos):
+    _parity(pf.poiseuille_case(eos, 0.71, 10, ny=NY, nx=NX))
+
+
+@pytest.mark.parametrize("eos", EOS)
+def test_couette_parity_with_oracle(eos):
+    _parity(pf.couette_case(eos, 0.71, 0.10, ny=NY, nx=NX))
+
+
+POISEUILLE = [(0.71, 0.1), (0.71, 100), (4.0, 10), (0.1, 10)]
+
+
+@pytest.mark.parametrize("Pr,Ec", POISEUILLE)
+@pytest.mark.parametrize("eos", EOS)
+def test_thermal_poiseuille_steady_state(eos, Pr, Ec):
+    if eos == "ideal" and Pr == 0.1:
+        pytest.skip("the paper's unstable set; see test_paper_unstable_sets_diverge")
+    c = pf.poiseuille_case(eos, Pr, Ec, ny=NY, nx=NX)
+    m, n = _steady(c)
+    W = NY - 1
+    u_an, th_an = pf.poiseuille_profiles(np.arange(NY) / W, Pr, Ec)
+    p = c["paper"]
+    u = m["ux"][:, 0] / p["U0"]
+    th = (m["T"][:, 0] - p["Tc"]) / (p["Th"] - p["Tc"])
+    rho = m["rho"][:, 0]
+    eu = np.abs(u - u_an).max()
+    eth = np.abs(th - th_an).max() / max(1.0, np.abs(th_an).max())
+    er = np.abs(rho / pf.density_profile(eos, m["T"][:, 0], float(NY)) - 1).max()
+    print(f"Poiseuille {eos} Pr={Pr} Ec={Ec}: {n} steps, u {eu:.2e} theta {eth:.2e} rho {er:.2e}", flush=True)
+    assert eu < 5e-3
+    assert eth < 1.2e-2
+    assert er < 1e-4
+
+
+COUETTE = [(0.71, 0.01), (0.71, 0.15), (1.0, 0.10), (0.1, 0.10)]
+
+
+@pytest.mark.parametrize("Pr,Ma", COUETTE)
+@pytest.mark.parametrize("eos", EOS)
+def test_thermal_couette_steady_state(eos, Pr, Ma):
+    if eos == "ideal" and Pr == 0.1:
+        pytest.skip("the paper's unstable set; see test_paper_unstable_sets_diverge")
+    c = pf.couette_case(eos, Pr, Ma, ny=NY, nx=NX)
+    m, n = _steady(c)
+    W = NY - 1
+    u_an, T_an = pf.couette_profiles(np.arange(NY) / W, Pr, Ma)
+    u = m["ux"][:, 0] / c["paper"]["U0"]
+    T = m["T"][:, 0]
+    rho = m["rho"][:, 0]
+    eu = np.abs(u - u_an).max()
+    eT = np.abs(T - T_an).max() / (T_an.max() - 1)
+    er = np.abs(rho / pf.density_profile(eos, T, float(NY)) - 1).max()
+    print(f"Couette {eos} Pr={Pr} Ma_e={Ma}: {n} steps, u {eu:.2e} T {eT:.2e} rho {er:.2e}", flush=True)
+    assert eu < 0.25 * Ma ** 2
+    assert eT < 0.8 * Ma ** 2
+    assert er < 1e-5
+
+
+@pytest.mark.parametrize("flow", ["poiseuille", "couette"])
+def test_paper_unstable_sets_diverge(flow, golden):
+    """Secs. 4.1 and 4.2: at (Ec = 10, Pr = 0.1) and (Ma_e = 0.10, Pr = 0.1)
+    the ideal-gas runs lose stability; the decoupling and Carnahan-Starling
+    runs at the same parameters do not."""
+    ref = golden["unstable_sets"][flow]
+    for eos in EOS:
+        if flow == "poiseuille":
+            c = pf.poiseuille_case(eos, ref["Pr"], ref["Ec"], ny=NY, nx=NX, Ma_lattice=ref["Ma_lattice"])
+        else:
+            c = pf.couette_case(eos, ref["Pr"], ref["Ma_e"], ny=NY, nx=NX)
+        g = lbm.Context(c).init()
+        diverged = False
+        try:
+            for _ in range(30):
+                g.step(10000)
+        except lbm.LBMError:
+            diverged = True
+        g.close()
+        print(f"{flow} {eos}: diverged={diverged}", flush=True)
+        assert diverged == (eos in ref["unstable_eos"]), eos

@@ -1,0 +1,95 @@
+"""The paper's channel validations (Secs. 4.1, 4.2) as pins of the CPU
+oracle: steady thermal Poiseuille and thermal Couette flows against their
+closed forms (eqs. Poiseuille.u.T, Couette.u.T) and the density of each
+equation of state (eq. rho.analytical), on a 33-row channel (W = 32) so that
+the suite stays fast.  The bars are the discretisation and lattice-Mach
+errors of that grid with margin: velocity to U0, temperature to the
+magnitude of its profile, density relative to the closed form.  A dropped
+viscous-heating or Y term moves the temperature by O(1) of its profile."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_flows as pf
+
+NY = 33
+
+
+def _steady(c, steps):
+    o = oracle.Oracle(c).init()
+    o.step(steps)
+    return o.macros()
+
+
+@pytest.mark.parametrize("eos", ["decoupled", "ideal", "cs"])
+def test_thermal_poiseuille_closed_form(eos, golden):
+    ref = golden["poiseuille_validation"]
+    Pr, Ec = ref["set_Pr"], ref["set_Ec"]
+    c = pf.poiseuille_case(eos, Pr, Ec, ny=NY, nx=1, Ma_lattice=ref["Ma_lattice"])
+    W = NY - 1
+    m = _steady(c, int(4 * W * W / pf.NU))
+    yy = np.arange(NY) / W
+    u_an, th_an = pf.poiseuille_profiles(yy, Pr, Ec)
+    p = c["paper"]
+    u = m["ux"][:, 0] / p["U0"]
+    th = (m["T"][:, 0] - p["Tc"]) / (p["Th"] - p["Tc"])
+    rho = m["rho"][:, 0]
+    rho_an = pf.density_profile(eos, m["T"][:, 0], float(NY))
+    eu, eth, er = np.abs(u - u_an).max(), np.abs(th - th_an).max() / np.abs(th_an).max(), np.abs(rho / rho_an - 1).max()
+    print(f"{eos}: u {eu:.2e} theta {eth:.2e} rho {er:.2e}")
+    assert eu < 6e-3
+    assert eth < 2.5e-2
+    assert er < 5e-4
+    # the densities differ by EOS as Sec. 4.1 describes: uniform for the
+    # decoupling EOS, the Carnahan-Starling fluid less compressible than the
+    # ideal gas
+    spread = rho.max() - rho.min()
+    assert spread < {"decoupled": 1e-3, "cs": 2e-3, "ideal": 1e-2}[eos]
+    if eos == "ideal":
+        assert spread > 2e-3
+
+
+@pytest.mark.parametrize("eos", ["decoupled", "ideal", "cs"])
+def test_thermal_couette_closed_form(eos, golden):
+    ref = golden["couette_validation"]
+    Pr, Ma = ref["set_Pr"], ref["set_Ma_e"]
+    c = pf.couette_case(eos, Pr, Ma, ny=NY, nx=1)
+    W = NY - 1
+    m = _steady(c, int(5 * W * W / (pf.NU / Pr)))
+    yy = np.arange(NY) / W
+    u_an, T_an = pf.couette_profiles(yy, Pr, Ma)
+    u = m["ux"][:, 0] / c["paper"]["U0"]
+    T = m["T"][:, 0]
+    rho = m["rho"][:, 0]
+    eu = np.abs(u - u_an).max()
+    eT = np.abs(T - T_an).max() / (T_an.max() - 1)
+    er = np.abs(rho / pf.density_profile(eos, T, float(NY)) - 1).max()
+    print(f"{eos}: u {eu:.2e} T {eT:.2e} rho {er:.2e}")
+    assert eu < 2e-3
+    assert eT < 6e-3
+    assert er < 1e-5
+    if eos == "ideal":
+        # rho/rho0 = A T0/T with A = 1 + Pr Ma_e^2 / 3 (Sec. 4.2), up to the
+        # node-sum normalisation of the lattice
+        A = 1 + Pr * Ma ** 2 / 3
+        assert np.abs(rho * T / A - 1).max() < 2e-3
+
+
+def test_closed_forms_are_consistent():
+    """The helpers themselves: the Couette cubic and its A (Sec. 4.2), and the
+    Poiseuille profile's values at the walls and at mid-channel."""
+    yy = np.linspace(0, 1, 2001)
+    for Pr, Ma in [(0.71, 0.15), (20, 0.1)]:
+        u, T = pf.couette_profiles(yy, Pr, Ma)
+        k = Pr * Ma ** 2
+        assert np.abs(u + 0.5 * k * (u - u ** 3 / 3) - (1 + k / 3) * yy).max() < 1e-13
+        assert abs(u[0]) < 1e-15 and abs(u[-1] - 1) < 1e-13
+        # A^-1 = int T0/T dy / W equals 1 / (1 + Pr Ma_e^2 / 3)
+        inv = np.trapezoid(1 / T, yy)
+        assert abs(inv * (1 + k / 3) - 1) < 1e-6
+    u, th = pf.poiseuille_profiles(np.array([0.0, 0.5, 1.0]), 0.71, 10)
+    assert np.allclose(u, [0, 1, 0]) and np.allclose(th, [0, 0.71 * 10 / 3 + 0.5, 1])
+    # Carnahan-Starling: c_s^2 = dp/drho = 1/3 at (rho0, T0) with the chosen R
+    R, h = pf.cs_R(), 1e-5
+    dp = ((1 + h) * pf.cs_Z(1 + h) - (1 - h) * pf.cs_Z(1 - h)) * R / (2 * h)
+    assert abs(dp - 1 / 3) < 1e-8
