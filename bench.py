@@ -217,7 +217,8 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(h["frac_hbm"], 4),
-            "traffic": measured_traffic() if head == "f32" else None,
+            # the committed counter record covers the FP32 kernel at 2048 x 2048
+            "traffic": measured_traffic() if head == "f32" and args.n == 2048 and args.seg_rows == 0 else None,
         },
         "paths": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in paths.items()},
