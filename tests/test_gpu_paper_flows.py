@@ -136,3 +136,34 @@ def test_paper_unstable_sets_diverge(flow, golden):
         g.close()
         print(f"{flow} {eos}: diverged={diverged}", flush=True)
         assert diverged == (eos in ref["unstable_eos"]), eos
+
+
+def _E(num, an):
+    """eq. Err: relative L2 error over the channel."""
+    return np.sqrt(((num - an) ** 2).sum() / (an ** 2).sum())
+
+
+@pytest.mark.parametrize("flow", ["poiseuille", "couette"])
+def test_velocity_error_order_in_lattice_mach(flow):
+    """The Mach study of Secs. 4.1-4.2 (Pr = 0.71) at the paper's grid: with
+    the cubic corrections the velocity error falls as Ma_lattice^4 where the
+    Mach error dominates (Couette at 0.08 -> 0.16, Poiseuille at 0.16 ->
+    0.32), without them as Ma_lattice^2."""
+    Mas = [0.16, 0.32] if flow == "poiseuille" else [0.08, 0.16]
+    E = {}
+    for cubic in (2, 0):
+        e = []
+        for Ma in Mas:
+            if flow == "poiseuille":
+                c = pf.poiseuille_case("ideal", 0.71, 100 * Ma ** 2, ny=NY, nx=4, Ma_lattice=Ma)
+                u_an = pf.poiseuille_profiles(np.arange(NY) / (NY - 1), 0.71, 100 * Ma ** 2)[0]
+            else:
+                c = pf.couette_case("decoupled", 0.71, Ma / np.sqrt(3.5), ny=NY, nx=4)
+                u_an = pf.couette_profiles(np.arange(NY) / (NY - 1), 0.71, Ma / np.sqrt(3.5))[0]
+            c["cubic"] = cubic
+            m, n = _steady(c, tol=1e-11)
+            e.append(_E(m["ux"][:, 0] / c["paper"]["U0"], u_an))
+        E[cubic] = np.log(e[1] / e[0]) / np.log(Mas[1] / Mas[0])
+        print(f"{flow} cubic={cubic}: E_u {e[0]:.3e} -> {e[1]:.3e}, order {E[cubic]:.2f}", flush=True)
+    assert E[2] > (3.3 if flow == "poiseuille" else 3.8)
+    assert E[0] < 2.1

@@ -93,3 +93,45 @@ def test_closed_forms_are_consistent():
     R, h = pf.cs_R(), 1e-5
     dp = ((1 + h) * pf.cs_Z(1 + h) - (1 - h) * pf.cs_Z(1 - h)) * R / (2 * h)
     assert abs(dp - 1 / 3) < 1e-8
+
+
+def _E(num, an):
+    """eq. Err: relative L2 error over the channel."""
+    return np.sqrt(((num - an) ** 2).sum() / (an ** 2).sum())
+
+
+def _mach_errors(flow, cubic, ny, Mas):
+    out = []
+    for Ma in Mas:
+        if flow == "poiseuille":
+            c = pf.poiseuille_case("ideal", 0.71, 100 * Ma ** 2, ny=ny, nx=1, Ma_lattice=Ma)
+            u_an = pf.poiseuille_profiles(np.arange(ny) / (ny - 1), 0.71, 100 * Ma ** 2)[0]
+        else:
+            c = pf.couette_case("decoupled", 0.71, Ma / np.sqrt(3.5), ny=ny, nx=1)
+            u_an = pf.couette_profiles(np.arange(ny) / (ny - 1), 0.71, Ma / np.sqrt(3.5))[0]
+        c["cubic"] = cubic
+        W = ny - 1
+        m = _steady(c, int(8 * W * W / (pf.NU / 0.71)))
+        out.append(_E(m["ux"][:, 0] / c["paper"]["U0"], u_an))
+    return np.array(out)
+
+
+def test_velocity_error_order_in_lattice_mach():
+    """Secs. 4.1-4.2 (Mach study, Pr = 0.71): with the cubic corrections of
+    Sec. 2.1 (R, T, X) the velocity error falls as Ma_lattice^4 once the
+    Mach error dominates (Couette, Ma_e = Ma_lattice / sqrt(3.5); Poiseuille,
+    Ec = 100 Ma_lattice^2, at its largest Mach numbers); without them it
+    falls only as Ma_lattice^2.  A wrong term in R, T or X loses the fourth
+    order."""
+    Mas = np.array([0.08, 0.16, 0.32])
+    order = lambda e: np.log(e[1:] / e[:-1]) / np.log(Mas[1:] / Mas[:-1])
+    c2 = _mach_errors("couette", 2, 17, Mas)
+    c0 = _mach_errors("couette", 0, 17, Mas)
+    print("couette", c2, order(c2), c0, order(c0))
+    assert (order(c2) > 3.6).all() and (order(c0) < 2.1).all()
+    assert (c0 / c2 > 5).all()
+    p2 = _mach_errors("poiseuille", 2, 33, Mas[1:])
+    p0 = _mach_errors("poiseuille", 0, 33, Mas[1:])
+    o2, o0 = np.log(p2[1] / p2[0]) / np.log(2), np.log(p0[1] / p0[0]) / np.log(2)
+    print("poiseuille", p2, o2, p0, o0)
+    assert o2 > 3.0 and o0 < 2.0
