@@ -312,12 +312,43 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
         bool edge;
     };
     std::vector<Cand> items;
-    double strip_rows = 0.0;   // cost-weighted strip-rows over all cases
-    for (int k = 0; k < nc; ++k) {
+    // Segment counts: the smallest bound T on the cost (rows, times xw_cost
+    // on edge strips) of one item such that all items fit the free slots;
+    // every strip is then cut into ceil(cost / T) segments (at least 4 rows
+    // each, 2 on edge strips), so that the longest item, which sets the
+    // step time, is as short as the slots allow.
+    auto seg_counts = [&](int k, double T, int& nseg, int& nseg_e) {
         const auto& P = c->P[k];
-        const int strips = P.nstrips, rows = P.wall_y ? P.ny - 2 : P.ny;
-        const int nedge = P.wall_x && xw_strips ? std::min(strips, 2) : 0;
-        strip_rows += (double(strips - nedge) + xw_cost * nedge) * rows;
+        const int rows = P.wall_y ? P.ny - 2 : P.ny;
+        if (seg_rows > 0) {
+            nseg = nseg_e = (rows + seg_rows - 1) / seg_rows;
+            return;
+        }
+        nseg = std::min(std::max(1, int(std::ceil(rows / T))), std::max(1, rows / 4));
+        nseg_e = std::min(std::max(1, int(std::ceil(xw_cost * rows / T))), std::max(1, rows / 2));
+    };
+    auto total_items = [&](double T) {
+        long long n = 0;
+        for (int k = 0; k < nc; ++k) {
+            const auto& P = c->P[k];
+            const int strips = P.nstrips, nedge = P.wall_x && xw_strips ? std::min(strips, 2) : 0;
+            int a, e;
+            seg_counts(k, T, a, e);
+            n += (long long)(strips - nedge) * a + (long long)nedge * e;
+        }
+        return n;
+    };
+    double T = 1.0;
+    if (seg_rows <= 0) {
+        double lo = 0.5, hi = 1.0;
+        for (int k = 0; k < nc; ++k) hi = std::max(hi, xw_cost * double(c->P[k].ny));
+        if (total_items(hi) <= budget) {
+            for (int it = 0; it < 60; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                (total_items(mid) <= budget ? hi : lo) = mid;
+            }
+        }
+        T = hi;
     }
     for (int k = 0; k < nc; ++k) {
         const auto& P = c->P[k];
@@ -325,14 +356,7 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
         const int rows = P.wall_y ? P.ny - 2 : P.ny, strips = P.nstrips;
         auto is_edge = [&](int st) { return xw_strips && P.wall_x && (st == 0 || st == strips - 1); };
         int nseg, nseg_e;
-        if (seg_rows > 0) {
-            nseg = nseg_e = (rows + seg_rows - 1) / seg_rows;
-        } else {
-            // this case's share of the resident slots, segments of >= 4 rows
-            nseg = int(std::max(1.0, std::floor(double(budget) * rows / strip_rows)));
-            nseg = std::min(nseg, std::max(1, rows / 4));
-            nseg_e = std::min(std::max(1, int(std::lround(xw_cost * nseg))), std::max(1, rows / 2));
-        }
+        seg_counts(k, T, nseg, nseg_e);
         const size_t first = items.size();
         for (int st = 0; st < strips; ++st) {
             const bool e = is_edge(st);
