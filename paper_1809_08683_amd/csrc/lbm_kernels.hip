@@ -60,9 +60,13 @@ using FmtF32G16 = Format<float, __half>;
 // such a strip relative to a plain row, and whether it loads the row two
 // ahead before the collision (where the registers allow it); the wavefronts
 // of a block (neighbouring strips of a segment share its CU).
+#ifndef LBM_PARK
+#define LBM_PARK 1
+#endif
 template <typename Fm> struct Tuning;
 template <> struct Tuning<FmtF64> {
     static constexpr int block_waves = 8;
+    static constexpr bool park = LBM_PARK != 0;
     static constexpr int waves = 2;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
     static constexpr bool xw_strips = false, xw_prefetch = false;
@@ -70,6 +74,7 @@ template <> struct Tuning<FmtF64> {
 };
 template <> struct Tuning<FmtF32> {
     static constexpr int block_waves = 4;
+    static constexpr bool park = LBM_PARK != 0;
     static constexpr int waves = 3;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
     static constexpr bool xw_strips = true, xw_prefetch = true;
@@ -77,6 +82,7 @@ template <> struct Tuning<FmtF32> {
 };
 template <> struct Tuning<FmtF32G16> {
     static constexpr int block_waves = 4;
+    static constexpr bool park = LBM_PARK != 0;
     static constexpr int waves = 3;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
     static constexpr bool xw_strips = true, xw_prefetch = true;
@@ -84,6 +90,7 @@ template <> struct Tuning<FmtF32G16> {
 };
 template <> struct Tuning<FmtF16> {
     static constexpr int block_waves = 8;
+    static constexpr bool park = LBM_PARK != 0;
     static constexpr int waves = 4;
     static constexpr bool lockstep = false, edge_select = false, alternate = false;
     static constexpr bool xw_strips = true, xw_prefetch = false;
@@ -494,7 +501,7 @@ __device__ __forceinline__ int stored_row(int v, int n, int walled)
 // stores of row y.
 template <typename Fm, bool EXPORT, bool XW>
 __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkItem w, const char* __restrict__ src_in,
-                                              char* __restrict__ dst_in)
+                                              char* __restrict__ dst_in, typename Fm::C* __restrict__ park)
 {
     const char* __restrict__ src = uniform_ptr(src_in);
     char* __restrict__ dst = uniform_ptr(dst_in);
@@ -599,6 +606,17 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
         pull(yf + d, f, g);
         row_state(yf + d, f, g, m_n, n_n, s_n);
     }
+    // The moments of the row ahead are not used before the next row: they
+    // wait in this wavefront's LDS slice, so that the collision of the
+    // current row has their registers.
+    auto park_store = [&](const C m[9], const C n[9]) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            park[q * WAVE + lane] = m[q];
+            park[(9 + q) * WAVE + lane] = n[q];
+        }
+    };
+    if constexpr (Tuning<Fm>::park) park_store(m_n, n_n);
 
     for (int i = 0; i < w.len; ++i) {
         if constexpr (Tuning<Fm>::lockstep) __syncthreads();
@@ -683,11 +701,12 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
         s_c = s_n;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            m_c[q] = m_n[q];
-            n_c[q] = n_n[q];
+            m_c[q] = Tuning<Fm>::park ? park[q * WAVE + lane] : m_n[q];
+            n_c[q] = Tuning<Fm>::park ? park[(9 + q) * WAVE + lane] : n_n[q];
         }
         if constexpr (XW && !Tuning<Fm>::xw_prefetch) pull(ynext, fr, gr);
         row_state(ynext, fr, gr, m_n, n_n, s_n);
+        if constexpr (Tuning<Fm>::park) park_store(m_n, n_n);
     }
 }
 
@@ -898,15 +917,18 @@ __attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
     if (w.kind == 0) {
         const char* src = static_cast<const char*>(P.buf[parity]);
         char* dst = static_cast<char*>(P.buf[parity ^ 1]);
+        using C = typename Fm::C;
+        __shared__ C park_lds[Tuning<Fm>::park ? Tuning<Fm>::block_waves * 18 * WAVE : 1];
+        C* park = park_lds + (Tuning<Fm>::park ? (threadIdx.x >> 6) * 18 * WAVE : 0);
         bool xw = false;
         if constexpr (Tuning<Fm>::xw_strips) xw = P.wall_x && (w.x0 == P.xlo || w.x0 + STRIP_COLS >= P.nx - 1);
         if constexpr (Tuning<Fm>::xw_strips) {
             if (xw) {
-                interior_item<Fm, EXPORT, true>(P, w, src, dst);
+                interior_item<Fm, EXPORT, true>(P, w, src, dst, park);
                 return;
             }
         }
-        interior_item<Fm, EXPORT, false>(P, w, src, dst);
+        interior_item<Fm, EXPORT, false>(P, w, src, dst, park);
     }
     else
         wall_item<Fm, EXPORT>(P, w, static_cast<const char*>(P.buf[parity]), static_cast<char*>(P.buf[parity ^ 1]));
