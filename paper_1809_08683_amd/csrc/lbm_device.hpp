@@ -594,6 +594,11 @@ template <typename S> struct Store;
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit data format, gfx9 CDNA
 constexpr int kDropOffset = int(0x80000000u);
+// Cache policy of the DF stores: non-temporal.  A post-collision row is read
+// again only in the next step, after the whole lattice has streamed through
+// the L2, so its lines are marked for early eviction and leave the L2 to the
+// source lines that neighbouring strips and segments read shortly after.
+constexpr int kStorePolicy = 2;
 
 // A pointer known to be the same in every lane, moved to scalar registers.
 template <typename T> __device__ __forceinline__ T* uniform_ptr(T* p)
@@ -620,7 +625,7 @@ template <> struct Store<double> {
     static __device__ __forceinline__ void bstore(rsrc_t r, int vo, int so, double v)
     {
         using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, kStorePolicy);
     }
 };
 template <> struct Store<float> {
@@ -633,7 +638,7 @@ template <> struct Store<float> {
     }
     static __device__ __forceinline__ void bstore(rsrc_t r, int vo, int so, float v)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, kStorePolicy);
     }
 };
 template <> struct Store<__half> {
@@ -654,7 +659,7 @@ template <> struct Store<__half> {
     }
     static __device__ __forceinline__ void bstore(rsrc_t r, int vo, int so, float v)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, vo, so, kStorePolicy);
     }
 };
 
