@@ -3,9 +3,12 @@ rows) at the grids of Table 1: eps = 0.6, Pr = 0.71, gamma = 1.4,
 Sutherland viscosity, first-order walls, FP64 path run to its steady state.
 The mean hot-wall Nusselt number and the mean pressure p_ave* (the integral
 of p_EOS / p0 over the cavity, trapezoidal weights on the node grid) must
-agree with the printed values to 0.5 % and 0.2 %; measured: 0.06-0.2 % and
-0.02-0.07 %.  (Ra >= 1e6 is out of reach at tau0 = 0.8, see the design
-notes.)"""
+agree with the printed values to 0.5 % and 0.2 % (measured: 0.06-0.2 % and
+0.02-0.07 %); the largest horizontal velocity on the vertical midplane and
+the largest vertical velocity on the horizontal midplane, in units of
+U_ref = sqrt(Ra) mu0 / (rho0 L), to 1 % (measured: up to 0.55 %), and their
+positions to one grid spacing (measured: up to half of one).  (Ra >= 1e6 is
+out of reach at tau0 = 0.8, see the design notes.)"""
 import numpy as np
 import pytest
 
@@ -25,13 +28,31 @@ def _steady_cavity(N, Ra, chunk=20000, cap=1000000, rtol=1e-7):
         if prev is not None and abs(nu - prev) < rtol * abs(nu):
             break
         prev = nu
-    p = g.macros()["p"]
+    m = g.macros()
+    p = m["p"]
     g.close()
     w = np.ones(N)
     w[0] = w[-1] = 0.5
     p0 = 1.0 / 3.0          # p_EOS(rho0, T0) = rho0 R T0 with R = c_s^2 / T0
     p_ave = float((w[:, None] * w[None, :] * p).sum() / w.sum() ** 2 / p0)
-    return nu, p_ave, n
+    # midplanes x = L/2 and y = L/2 lie halfway between two node lines (N even)
+    L = N - 1
+    Uref = np.sqrt(Ra) * c["nu0"] / L
+    ux_mid = 0.5 * (m["ux"][:, N // 2 - 1] + m["ux"][:, N // 2]) / Uref
+    uy_mid = 0.5 * (m["uy"][N // 2 - 1, :] + m["uy"][N // 2, :]) / Uref
+    return nu, p_ave, n, _peak(ux_mid, L), _peak(uy_mid, L)
+
+
+def _peak(v, L):
+    """Largest |v| on a midplane line and its position x / L, refined by the
+    parabola through the three nodes around the largest node value."""
+    a = np.abs(v)
+    i = int(np.argmax(a))
+    if 0 < i < len(a) - 1:
+        d = a[i - 1] - 2 * a[i] + a[i + 1]
+        off = 0.5 * (a[i - 1] - a[i + 1]) / d if d != 0 else 0.0
+        return a[i] - 0.25 * (a[i - 1] - a[i + 1]) * off, (i + off) / L
+    return a[i], i / L
 
 
 @pytest.mark.parametrize("Ra", [1e3, 1e4, 1e5])
@@ -39,9 +60,15 @@ def test_cavity_against_table2(Ra, golden):
     t1, t2 = golden["cavity_table1"], golden["cavity_table2_present"]
     N = t1["N"][t1["Ra"].index(Ra)]
     i = t2["Ra"].index(Ra)
-    nu, p_ave, n = _steady_cavity(N, Ra)
+    nu, p_ave, n, (ux, y), (uy, x) = _steady_cavity(N, Ra)
     e_nu = (nu - t2["Nu_ave"][i]) / t2["Nu_ave"][i]
     e_p = (p_ave - t2["p_ave"][i]) / t2["p_ave"][i]
-    print(f"Ra={Ra:.0e} N={N}: {n} steps, Nu {nu:.5f} ({e_nu:+.2e}), p_ave {p_ave:.5f} ({e_p:+.2e})", flush=True)
+    j = t2["velocity_rows_Ra"].index(Ra)
+    print(f"Ra={Ra:.0e} N={N}: {n} steps, Nu {nu:.5f} ({e_nu:+.2e}), p_ave {p_ave:.5f} ({e_p:+.2e}), "
+          f"|ux|max {ux:.4f} at y {y:.4f}, |uy|max {uy:.4f} at x {x:.4f}", flush=True)
     assert abs(e_nu) < 5e-3
     assert abs(e_p) < 2e-3
+    assert abs(ux - t2["ux_max"][j]) < 0.01 * t2["ux_max"][j]
+    assert abs(uy - t2["uy_max"][j]) < 0.01 * t2["uy_max"][j]
+    assert abs(y - t2["y_max"][j]) < 1.0 / (N - 1)
+    assert abs(x - t2["x_max"][j]) < 1.0 / (N - 1)
