@@ -301,22 +301,35 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
         for (int k = 0; k < nc; ++k)
             for (int b = 0; b < nwall[k]; b += chunk) wall.push_back({k, 1, b, 0, std::min(chunk, nwall[k] - b), 0});
     }
-    const long long budget = std::max<long long>(capacity - (long long)wall.size(), 1);
+    // Wall item i goes to slot i / nblocks of block i % nblocks (one per block
+    // first, spreading them over the CUs).  When interior waves march in
+    // lockstep, a block must not mix them with wall waves: wall items then
+    // fill whole blocks of their own, spread over the XCDs.
+    std::vector<int> used(size_t(nblocks), 0);
+    std::vector<std::pair<long long, lbm::WorkItem>> wall_placed;
+    for (size_t i = 0; i < wall.size(); ++i) {
+        long long blk = lockstep ? (long long)(i / PB) : (long long)i % nblocks;
+        while (blk < (long long)used.size() && used[size_t(blk)] >= PB) ++blk;
+        while (blk >= (long long)used.size()) used.push_back(0);
+        wall_placed.push_back({blk * PB + used[size_t(blk)], wall[i]});
+        ++used[size_t(blk)];
+    }
+    if (lockstep)
+        for (auto& u : used)
+            if (u > 0) u = PB;
+    const long long wall_blocks = (long long)used.size();
+
     // Interior items in (case, first row, strip) order; the edge strips of a
     // walled-x case (first and last) also collide the x-wall nodes, so a row
-    // of theirs costs xw_cost plain rows: by default they get that many
-    // times more (shorter) segments.
+    // of theirs costs xw_cost plain rows.
     struct Cand {
         lbm::WorkItem w;
         double cost;
         bool edge;
     };
-    std::vector<Cand> items;
-    // Segment counts: the smallest bound T on the cost (rows, times xw_cost
-    // on edge strips) of one item such that all items fit the free slots;
-    // every strip is then cut into ceil(cost / T) segments (at least 4 rows
-    // each, 2 on edge strips), so that the longest item, which sets the
-    // step time, is as short as the slots allow.
+    // Segment counts for a bound T on the cost (rows, times xw_cost on edge
+    // strips) of one item: every strip is cut into ceil(cost / T) segments
+    // (at least 4 rows each, 2 on edge strips).
     auto seg_counts = [&](int k, double T, int& nseg, int& nseg_e) {
         const auto& P = c->P[k];
         const int rows = P.wall_y ? P.ny - 2 : P.ny;
@@ -327,78 +340,42 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
         nseg = std::min(std::max(1, int(std::ceil(rows / T))), std::max(1, rows / 4));
         nseg_e = std::min(std::max(1, int(std::ceil(xw_cost * rows / T))), std::max(1, rows / 2));
     };
-    auto total_items = [&](double T) {
-        long long n = 0;
+    auto make_items = [&](double T) {
+        std::vector<Cand> items;
         for (int k = 0; k < nc; ++k) {
             const auto& P = c->P[k];
-            const int strips = P.nstrips, nedge = P.wall_x && xw_strips ? std::min(strips, 2) : 0;
-            int a, e;
-            seg_counts(k, T, a, e);
-            n += (long long)(strips - nedge) * a + (long long)nedge * e;
+            const int xlo = P.wall_x, ylo = P.wall_y;
+            const int rows = P.wall_y ? P.ny - 2 : P.ny, strips = P.nstrips;
+            auto is_edge = [&](int st) { return xw_strips && P.wall_x && (st == 0 || st == strips - 1); };
+            int nseg, nseg_e;
+            seg_counts(k, T, nseg, nseg_e);
+            const size_t first = items.size();
+            for (int st = 0; st < strips; ++st) {
+                const bool e = is_edge(st);
+                const int n = e ? nseg_e : nseg;
+                for (int g = 0; g < n; ++g) {
+                    const int y0 = ylo + int((long long)rows * g / n);
+                    const int y1 = ylo + int((long long)rows * (g + 1) / n);
+                    if (y1 <= y0) continue;
+                    items.push_back({{k, 0, xlo + lbm::STRIP_COLS * st, y0, y1 - y0, g & 1},
+                                     double(y1 - y0) * (e ? xw_cost : 1.0), e});
+                }
+            }
+            std::stable_sort(items.begin() + first, items.end(), [](const Cand& a, const Cand& b) {
+                return a.w.y0 != b.w.y0 ? a.w.y0 < b.w.y0 : a.w.x0 < b.w.x0;
+            });
         }
-        return n;
+        return items;
     };
-    double T = 1.0;
-    if (seg_rows <= 0) {
-        double lo = 0.5, hi = 1.0;
-        for (int k = 0; k < nc; ++k) hi = std::max(hi, xw_cost * double(c->P[k].ny));
-        if (total_items(hi) <= budget) {
-            for (int it = 0; it < 60; ++it) {
-                const double mid = 0.5 * (lo + hi);
-                (total_items(mid) <= budget ? hi : lo) = mid;
-            }
-        }
-        T = hi;
-    }
-    for (int k = 0; k < nc; ++k) {
-        const auto& P = c->P[k];
-        const int xlo = P.wall_x, ylo = P.wall_y;
-        const int rows = P.wall_y ? P.ny - 2 : P.ny, strips = P.nstrips;
-        auto is_edge = [&](int st) { return xw_strips && P.wall_x && (st == 0 || st == strips - 1); };
-        int nseg, nseg_e;
-        seg_counts(k, T, nseg, nseg_e);
-        const size_t first = items.size();
-        for (int st = 0; st < strips; ++st) {
-            const bool e = is_edge(st);
-            const int n = e ? nseg_e : nseg;
-            for (int g = 0; g < n; ++g) {
-                const int y0 = ylo + int((long long)rows * g / n);
-                const int y1 = ylo + int((long long)rows * (g + 1) / n);
-                if (y1 <= y0) continue;
-                items.push_back({{k, 0, xlo + lbm::STRIP_COLS * st, y0, y1 - y0, g & 1},
-                                 double(y1 - y0) * (e ? xw_cost : 1.0), e});
-            }
-        }
-        std::stable_sort(items.begin() + first, items.end(), [](const Cand& a, const Cand& b) {
-            return a.w.y0 != b.w.y0 ? a.w.y0 < b.w.y0 : a.w.x0 < b.w.x0;
-        });
-    }
-    // Wall item i goes to slot i / nblocks of block i % nblocks (one per block
-    // first, spreading them over the CUs).  When interior waves march in
-    // lockstep, a block must not mix them with wall waves: wall items then
-    // fill whole blocks of their own, spread over the XCDs.
-    std::vector<int> used(size_t(nblocks), 0);
-    std::vector<std::pair<long long, lbm::WorkItem>> placed;
-    for (size_t i = 0; i < wall.size(); ++i) {
-        long long blk = lockstep ? (long long)(i / PB) : (long long)i % nblocks;
-        while (blk < (long long)used.size() && used[size_t(blk)] >= PB) ++blk;
-        while (blk >= (long long)used.size()) used.push_back(0);
-        placed.push_back({blk * PB + used[size_t(blk)], wall[i]});
-        ++used[size_t(blk)];
-    }
-    if (lockstep)
-        for (auto& u : used)
-            if (u > 0) u = PB;
-    const long long wall_blocks = (long long)used.size();
     // Band k (the items whose cost midpoint lies in the k-th eighth of the
     // total, a contiguous run of rows) fills the free slots of blocks k,
     // k + 8, ... of XCD k; with lockstep its edge items first fill blocks of
     // their own, as their rows take longer.  Blocks past the resident count
-    // are added if a band needs them.
-    double total_cost = 0.0;
-    for (const auto& it : items) total_cost += it.cost;
-    std::vector<std::vector<size_t>> band(NX);
-    {
+    // are added if a band needs them.  Returns the blocks the launch needs.
+    auto place = [&](const std::vector<Cand>& items, std::vector<std::pair<long long, lbm::WorkItem>>* out) {
+        double total_cost = 0.0;
+        for (const auto& it : items) total_cost += it.cost;
+        std::vector<std::vector<size_t>> band(NX);
         double acc = 0.0;
         for (size_t i = 0; i < items.size(); ++i) {
             const double mid = acc + 0.5 * items[i].cost;
@@ -406,30 +383,50 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
             const int k = std::min(NX - 1, int(mid / std::max(total_cost, 1e-300) * NX));
             band[size_t(k)].push_back(i);
         }
-    }
-    long long total_blocks = (long long)round_up(size_t(wall_blocks), NX);
-    for (int k = 0; k < NX; ++k) {
-        long long blk = k;
-        int fill = blk < wall_blocks ? used[size_t(blk)] : 0;
-        auto put = [&](const lbm::WorkItem& w) {
-            while (fill >= PB) {
-                blk += NX;
-                fill = blk < wall_blocks ? used[size_t(blk)] : 0;
+        long long total_blocks = (long long)round_up(size_t(wall_blocks), NX);
+        for (int k = 0; k < NX; ++k) {
+            long long blk = k;
+            int fill = blk < wall_blocks ? used[size_t(blk)] : 0;
+            auto put = [&](const lbm::WorkItem& w) {
+                while (fill >= PB) {
+                    blk += NX;
+                    fill = blk < wall_blocks ? used[size_t(blk)] : 0;
+                }
+                if (out) out->push_back({blk * PB + fill, w});
+                ++fill;
+                total_blocks = std::max(total_blocks, (blk / NX + 1) * NX);
+            };
+            if (lockstep) {
+                for (size_t i : band[size_t(k)])
+                    if (items[i].edge) put(items[i].w);
+                if (fill > 0) fill = PB;   // blocks of edge items hold nothing else
+                for (size_t i : band[size_t(k)])
+                    if (!items[i].edge) put(items[i].w);
+            } else {
+                for (size_t i : band[size_t(k)]) put(items[i].w);
             }
-            placed.push_back({blk * PB + fill, w});
-            ++fill;
-            total_blocks = std::max(total_blocks, (blk / NX + 1) * NX);
-        };
-        if (lockstep) {
-            for (size_t i : band[size_t(k)])
-                if (items[i].edge) put(items[i].w);
-            if (fill > 0) fill = PB;   // blocks of edge items hold nothing else
-            for (size_t i : band[size_t(k)])
-                if (!items[i].edge) put(items[i].w);
-        } else {
-            for (size_t i : band[size_t(k)]) put(items[i].w);
         }
+        return total_blocks;
+    };
+    // The smallest T whose items all fit the resident blocks (one round of
+    // wavefronts): the longest item, which sets the step time, is then as
+    // short as the device allows.
+    double T = 1.0;
+    if (seg_rows <= 0) {
+        double lo = 0.5, hi = 1.0;
+        for (int k = 0; k < nc; ++k) hi = std::max(hi, xw_cost * double(c->P[k].ny));
+        auto fits = [&](double t) { return place(make_items(t), nullptr) <= nblocks; };
+        if (fits(hi)) {
+            for (int it = 0; it < 40; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                (fits(mid) ? hi : lo) = mid;
+            }
+        }
+        T = hi;
     }
+    const std::vector<Cand> items = make_items(T);
+    std::vector<std::pair<long long, lbm::WorkItem>> placed = wall_placed;
+    const long long total_blocks = place(items, &placed);
     c->work.assign(size_t(total_blocks * PB), lbm::WorkItem{0, 2, 0, 0, 0, 0});
     for (const auto& pr : placed) {
         if (pr.first < 0 || pr.first >= (long long)c->work.size() || c->work[size_t(pr.first)].kind != 2) return false;

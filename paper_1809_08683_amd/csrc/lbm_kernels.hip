@@ -78,7 +78,7 @@ template <> struct Tuning<FmtF32> {
     static constexpr int waves = 3;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
     static constexpr bool xw_strips = true, xw_prefetch = true;
-    static constexpr double xw_cost = 1.65;
+    static constexpr double xw_cost = 1.15;
 };
 template <> struct Tuning<FmtF32G16> {
     static constexpr int block_waves = 4;
@@ -86,7 +86,7 @@ template <> struct Tuning<FmtF32G16> {
     static constexpr int waves = 3;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
     static constexpr bool xw_strips = true, xw_prefetch = true;
-    static constexpr double xw_cost = 1.45;
+    static constexpr double xw_cost = 1.3;
 };
 template <> struct Tuning<FmtF16> {
     static constexpr int block_waves = 8;
@@ -94,7 +94,7 @@ template <> struct Tuning<FmtF16> {
     static constexpr int waves = 4;
     static constexpr bool lockstep = false, edge_select = false, alternate = false;
     static constexpr bool xw_strips = true, xw_prefetch = false;
-    static constexpr double xw_cost = 3.0;
+    static constexpr double xw_cost = 2.5;
 };
 static_assert(REGION_SLOTS == WAVE && STRIP_COLS == WAVE - 4, "one wavefront per strip region");
 
@@ -1155,7 +1155,7 @@ int launch_copy(const void* src, void* dst, long long bytes, hipStream_t stream)
 
 // Calls fn with a value of the storage format of a precision code.
 template <typename Fn>
-int with_format(int prec, Fn&& fn)
+auto with_format(int prec, Fn&& fn)
 {
     switch (prec) {
     case PREC_F64: return fn(FmtF64{});
