@@ -276,14 +276,14 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
     }
     std::vector<lbm::WorkItem> wall;
     if (total_wall > 0) {
-        // Wall wavefronts get the share of the slots that their work needs:
-        // a wall node costs about kWallCost interior nodes (its own pull, the
+        // A wall node costs about kWallCost interior nodes (its own pull, the
         // pulls at x_f, x_ff along the inner normal and of its gradient
-        // neighbours, the inversions).  A wavefront takes its nodes 64 at a
-        // time: chunks of wall rows are whole multiples of 64.  The nodes of
-        // x-wall columns (one cache line per node and DF row) are spread
-        // over at least one wavefront per CU while that leaves 16 or more
-        // nodes to each.
+        // neighbours, the inversions).  A wavefront takes wall-row nodes 64
+        // at a time, in chunks of whole passes that last about as long as an
+        // interior item.  The nodes of x-wall columns (one cache line per
+        // node and DF row) get the wavefronts their cost share of the slots
+        // asks for, at least one per CU while that leaves 16 or more nodes
+        // to each.
         constexpr double kWallCost = 12.0;
         const double interior = double(total_cells) * lbm::STRIP_COLS;
         const double frac = kWallCost * double(total_wall) / (kWallCost * double(total_wall) + interior);
@@ -295,8 +295,13 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
             nw = std::max(nw, std::min<long long>(cus, (total_wall + 15) / 16));
             chunk = int((total_wall + nw - 1) / nw);
         } else {
-            const long long per = (total_wall + nw - 1) / nw;
-            chunk = int((per + lbm::REGION_SLOTS - 1) / lbm::REGION_SLOTS * lbm::REGION_SLOTS);   // 64 lanes
+            // whole passes of 64 nodes, as many as make a wall item about as
+            // long as an interior item (a pass costs kWallCost * 64 / 60 rows)
+            const double pass_rows = kWallCost * lbm::REGION_SLOTS / lbm::STRIP_COLS;
+            const double item_rows = (double(total_cells) + pass_rows * double(total_wall) / lbm::REGION_SLOTS) /
+                                     double(capacity);
+            const long long passes = std::max<long long>(1, std::llround(item_rows / pass_rows));
+            chunk = int(passes * lbm::REGION_SLOTS);
         }
         for (int k = 0; k < nc; ++k)
             for (int b = 0; b < nwall[k]; b += chunk) wall.push_back({k, 1, b, 0, std::min(chunk, nwall[k] - b), 0});
