@@ -164,8 +164,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU slab decomposition is "
-              "described in DESIGN.md but not built); use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (a multi-GPU slab decomposition is designed "
+              "but not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
