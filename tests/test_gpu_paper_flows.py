@@ -167,3 +167,39 @@ def test_velocity_error_order_in_lattice_mach(flow):
         print(f"{flow} cubic={cubic}: E_u {e[0]:.3e} -> {e[1]:.3e}, order {E[cubic]:.2f}", flush=True)
     assert E[2] > (3.3 if flow == "poiseuille" else 3.8)
     assert E[0] < 2.1
+
+
+def test_temperature_density_error_order_in_lattice_mach():
+    """The same Mach study for the temperature and the density (Sec. 4.1,
+    ideal gas, Pr = 0.71, Ec = 100 Ma_lattice^2): both errors of eq. Err
+    fall as Ma_lattice^2 (measured local orders 1.95-2.00 between 0.01 and
+    0.08).  The density is compared with eq. rho.analytical evaluated on the
+    closed-form temperature."""
+    Mas = [0.02, 0.04]
+    eT, er = [], []
+    yy = np.arange(NY) / (NY - 1)
+    for Ma in Mas:
+        Ec = 100 * Ma ** 2
+        c = pf.poiseuille_case("ideal", 0.71, Ec, ny=NY, nx=4, Ma_lattice=Ma)
+        g = lbm.Context(c).init()
+        prev, n = None, 0
+        while n < 600000:
+            g.step(20000)
+            n += 20000
+            m = g.macros()
+            cur = np.concatenate([m["ux"][:, 0], m["T"][:, 0], m["rho"][:, 0]])
+            if prev is not None and np.abs(cur - prev).max() < 1e-11 * np.abs(cur).max():
+                break
+            prev = cur
+        g.close()
+        p = c["paper"]
+        th_an = pf.poiseuille_profiles(yy, 0.71, Ec)[1]
+        T_an = p["Tc"] + th_an * (p["Th"] - p["Tc"])
+        eT.append(_E((m["T"][:, 0] - p["Tc"]) / (p["Th"] - p["Tc"]), th_an))
+        er.append(_E(m["rho"][:, 0], pf.density_profile("ideal", T_an, float(NY))))
+        print(f"Ma {Ma}: {n} steps, E_T {eT[-1]:.3e} E_rho {er[-1]:.3e}", flush=True)
+    oT = np.log(eT[1] / eT[0]) / np.log(2)
+    orho = np.log(er[1] / er[0]) / np.log(2)
+    print(f"orders: T {oT:.2f} rho {orho:.2f}", flush=True)
+    assert 1.8 < oT < 2.2
+    assert 1.8 < orho < 2.2

@@ -135,3 +135,25 @@ def test_velocity_error_order_in_lattice_mach():
     o2, o0 = np.log(p2[1] / p2[0]) / np.log(2), np.log(p0[1] / p0[0]) / np.log(2)
     print("poiseuille", p2, o2, p0, o0)
     assert o2 > 3.0 and o0 < 2.0
+
+
+def test_temperature_density_error_order_in_lattice_mach():
+    """Sec. 4.1, Mach study for the temperature and the density (ideal gas,
+    Pr = 0.71, Ec = 100 Ma_lattice^2, 33 rows): the errors of eq. Err fall as
+    Ma_lattice^2 (measured orders 1.95 and 2.00 from 0.02 to 0.04)."""
+    ny, W = 33, 32
+    yy = np.arange(ny) / W
+    eT, er = [], []
+    for Ma in (0.02, 0.04):
+        Ec = 100 * Ma ** 2
+        c = pf.poiseuille_case("ideal", 0.71, Ec, ny=ny, nx=1, Ma_lattice=Ma)
+        m = _steady(c, int(4 * W * W / (pf.NU / 0.71)))
+        p = c["paper"]
+        th_an = pf.poiseuille_profiles(yy, 0.71, Ec)[1]
+        T_an = p["Tc"] + th_an * (p["Th"] - p["Tc"])
+        eT.append(_E((m["T"][:, 0] - p["Tc"]) / (p["Th"] - p["Tc"]), th_an))
+        er.append(_E(m["rho"][:, 0], pf.density_profile("ideal", T_an, float(ny))))
+    oT, orho = np.log(eT[1] / eT[0]) / np.log(2), np.log(er[1] / er[0]) / np.log(2)
+    print(eT, er, oT, orho)
+    assert 1.8 < oT < 2.2
+    assert 1.8 < orho < 2.2
