@@ -375,7 +375,8 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
     // Band k (the items whose cost midpoint lies in the k-th eighth of the
     // total, a contiguous run of rows) fills the free slots of blocks k,
     // k + 8, ... of XCD k; with lockstep its edge items first fill blocks of
-    // their own, as their rows take longer.  Blocks past the resident count
+    // their own, as their rows take longer, and without it they are spaced
+    // evenly among the band's other items.  Blocks past the resident count
     // are added if a band needs them.  Returns the blocks the launch needs.
     auto place = [&](const std::vector<Cand>& items, std::vector<std::pair<long long, lbm::WorkItem>>* out) {
         double total_cost = 0.0;
@@ -408,7 +409,16 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
                 for (size_t i : band[size_t(k)])
                     if (!items[i].edge) put(items[i].w);
             } else {
-                for (size_t i : band[size_t(k)]) put(items[i].w);
+                // edge items spread evenly through the band, so that no CU
+                // holds more than its share of their heavier rows
+                std::vector<size_t> e_i, r_i;
+                for (size_t i : band[size_t(k)]) (items[i].edge ? e_i : r_i).push_back(i);
+                const size_t N = e_i.size() + r_i.size(), E = e_i.size();
+                size_t ie = 0, ir = 0;
+                for (size_t p = 0; p < N; ++p) {
+                    const bool take_e = ie < E && (ir >= r_i.size() || (2 * ie + 1) * N <= (2 * p + 1) * E);
+                    put(items[take_e ? e_i[ie++] : r_i[ir++]].w);
+                }
             }
         }
         return total_blocks;

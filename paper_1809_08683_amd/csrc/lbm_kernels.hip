@@ -94,7 +94,7 @@ template <> struct Tuning<FmtF16> {
     static constexpr int waves = 4;
     static constexpr bool lockstep = false, edge_select = false, alternate = false;
     static constexpr bool xw_strips = true, xw_prefetch = false;
-    static constexpr double xw_cost = 2.5;
+    static constexpr double xw_cost = 2.0;
 };
 static_assert(REGION_SLOTS == WAVE && STRIP_COLS == WAVE - 4, "one wavefront per strip region");
 
