@@ -52,8 +52,13 @@ Layout layout_of(int nx, int ny, int prec)
 {
     Layout L;
     // enough 64-slot strip regions for the off-wall columns of either kind of
-    // x boundary (periodic needs ceil(nx / 60), walled ceil((nx - 2) / 60))
-    L.pitch = ((nx + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS) * lbm::REGION_SLOTS;
+    // x boundary (periodic needs ceil(nx / 60), walled ceil((nx - 2) / 60)).
+    // FP32 rows carry two more regions that nothing reads or writes: with the
+    // longer row stride the step ran 1.5-1.8 % faster on a 2048^2 grid (and
+    // unchanged on 4096^2), as the rows a step touches at once fall on the
+    // HBM channels more evenly; for the other formats no pad measured better.
+    L.pitch = ((nx + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS) * lbm::REGION_SLOTS +
+              (prec == LBM_FP32 ? 2 * lbm::REGION_SLOTS : 0);
     L.plane = (long long)(ny + 2) * L.pitch;
     L.buf_bytes = round_up(size_t(9) * L.plane * (f_size(prec) + g_size(prec)), 256);
     L.macro_bytes = round_up(size_t(5) * nx * ny * sizeof(double), 256);
@@ -231,7 +236,8 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
     P.cubic = o.cubic;
     P.extrap_order = bc.extrap_order;
     for (int s = 0; s < 4; ++s) P.side_adiabatic[s] = bc.side[s].adiabatic ? 1 : 0;
-    // every stored row, and so every 64-slot strip region, starts 256-byte aligned
+    // the buffers start 256-byte aligned and a row is a whole number of 64-slot
+    // regions, so every strip region starts on a 128-byte cache line
     P.buf[0] = base;
     P.buf[1] = base + L.buf_bytes;
     P.macro = reinterpret_cast<double*>(base + 2 * L.buf_bytes);
