@@ -19,8 +19,6 @@ OK, EINVAL, ENOMEM, EDEVICE, EDIVERGED, ESTATE = 0, -1, -2, -3, -4, -5
 EOS = {"decoupled": 0, "ideal": 1, "vdw": 2, "cs": 3}
 VISC = {"const": 0, "linear": 1, "sutherland": 2}
 PREC = {"f64": 0, "f32": 1, "f16s": 2, "f32g16": 3}
-# bytes of one stored (f, g) value pair
-PAIR_BYTES = {"f64": 16, "f32": 8, "f16s": 4, "f32g16": 6}
 
 
 class LibraryMissing(RuntimeError):
