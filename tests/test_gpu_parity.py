@@ -194,6 +194,27 @@ def test_cavity_2048_full_grid(prec):
     compare(g.macros(), o.macros(), prec, f"cavity 2048 x 2 {prec}")
 
 
+_REF4096 = {}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s", "f32g16"])
+def test_cavity_4096_full_grid(prec):
+    """The largest configuration: the 4096^2 cavity (the paper's grid for
+    Ra = 1e8; 69 strips, segments about twice as tall as at 2048^2), 2 steps
+    from random fields, every node compared with the oracle (computed once)."""
+    c = inputs.cavity(N=4096, Ra=1e8, prec=prec)
+    fields = inputs.random_fields(c, 6, du=0.01, drho=0.02, dT=0.02)
+    print(f"case 4096x4096 prec={prec} steps=2 seed=6", flush=True)
+    g = lbm.Context(c).init(**fields).step(2)
+    mg = g.macros()
+    g.close()
+    if not _REF4096:
+        o = oracle.Oracle(c).init(**fields).step(2)
+        _REF4096.update(o.macros())
+        del o
+    compare(mg, _REF4096, prec, f"cavity 4096 x 2 {prec}")
+
+
 # ---------------------------------------------------------------- reductions
 def test_nusselt_and_totals_match_oracle():
     c = _cavity(33, ny=29)
