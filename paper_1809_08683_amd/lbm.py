@@ -199,8 +199,12 @@ class _Base:
         return self
 
     def step_timed(self, n: int, allow_diverged: bool = False) -> float:
+        """Advance n steps; return their device time (ms).  With
+        allow_diverged a divergence is recorded in ``self.diverged`` instead
+        of raised."""
         ms = C.c_double(0.0)
         rc = self.lib.lbm_step_timed(self.h, int(n), C.byref(ms))
+        self.diverged = rc == EDIVERGED
         if not (rc == EDIVERGED and allow_diverged):
             self._check(rc, "lbm_step_timed")
         return ms.value
