@@ -174,6 +174,7 @@ class _Base:
     def __init__(self):
         self.lib = load_library()
         self.h = C.c_void_p()
+        self.diverged = False
 
     def _check(self, rc, what):
         if rc == OK:
