@@ -13,7 +13,7 @@
  *     -> extrapolation -> inversion -> rebuild of all 18 DFs.
  *
  * Readings where the paper is silent (the same readings the HIP library
- * uses; each is listed with its reason in the design notes):
+ * uses):
  *   - gradients in T.grad(rho) and X.grad(p): isotropic 9-point central
  *     difference at nodes off the walls; at wall nodes a second-order
  *     one-sided difference along a walled axis and a two-point central
