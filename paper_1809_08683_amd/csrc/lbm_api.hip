@@ -260,8 +260,8 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
 // lockstep every wall wavefront goes to a block of its own, so that each CU
 // carries the same mix of wall and interior work; with lockstep the wall
 // wavefronts fill blocks of their own.  Block b runs on XCD b % 8; the
-// interior items of one contiguous band of rows go to the blocks of one XCD,
-// neighbouring strips of a segment sharing a block.
+// interior items of a few contiguous bands of rows go to the blocks of one
+// XCD, neighbouring strips of a segment sharing a block.
 bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bool lockstep, bool xw_strips,
                 double xw_cost)
 {
@@ -377,12 +377,15 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
         }
         return items;
     };
-    // Band k (the items whose cost midpoint lies in the k-th eighth of the
-    // total, a contiguous run of rows) fills the free slots of blocks k,
-    // k + 8, ... of XCD k; with lockstep its edge items first fill blocks of
-    // their own, as their rows take longer, and without it they are spaced
-    // evenly among the band's other items.  Blocks past the resident count
-    // are added if a band needs them.  Returns the blocks the launch needs.
+    // The items are cut by their cost midpoints into kBands bands of equal
+    // cost, each a contiguous run of rows; band j goes to XCD j % 8, whose
+    // items fill the free slots of its blocks k, k + 8, ...  (Four bands per
+    // XCD measured 0.6-1.7 % faster than one in FP32 and the same in the
+    // other formats.)  With lockstep an XCD's edge items first fill blocks
+    // of their own, as their rows take longer; without it they are spaced
+    // evenly among its other items.  Blocks past the resident count are
+    // added if an XCD needs them.  Returns the blocks the launch needs.
+    constexpr int kBands = 4 * NX;
     auto place = [&](const std::vector<Cand>& items, std::vector<std::pair<long long, lbm::WorkItem>>* out) {
         double total_cost = 0.0;
         for (const auto& it : items) total_cost += it.cost;
@@ -391,7 +394,8 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
         for (size_t i = 0; i < items.size(); ++i) {
             const double mid = acc + 0.5 * items[i].cost;
             acc += items[i].cost;
-            const int k = std::min(NX - 1, int(mid / std::max(total_cost, 1e-300) * NX));
+            const int j = std::min(kBands - 1, int(mid / std::max(total_cost, 1e-300) * kBands));
+            const int k = j % NX;
             band[size_t(k)].push_back(i);
         }
         long long total_blocks = (long long)round_up(size_t(wall_blocks), NX);
