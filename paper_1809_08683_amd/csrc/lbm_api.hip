@@ -247,7 +247,6 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
     const double cv = o.cv_rule ? cp - pressure(e, R, e.rho0, e.T0) / (e.rho0 * e.T0) : cp / gamma;
     fill_coef<double>(P.cd, e, R, cp, cv, Pr, r, o, bc);
     fill_coef<float>(P.cf, e, R, cp, cv, Pr, r, o, bc);
-
 }
 
 // Work decomposition of one step.  The off-wall region of every case is cut
@@ -257,9 +256,9 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
 // allows it, the strips next to an x-wall also collide its nodes (with
 // shorter segments, as their rows cost more); the other wall nodes go to
 // wall items, split over wavefronts in proportion to their cost.  Without
-// lockstep every wall wavefront goes to a block of its own, so that each CU
-// carries the same mix of wall and interior work; with lockstep the wall
-// wavefronts fill blocks of their own.  Block b runs on XCD b % 8; the
+// lockstep the wall wavefronts are spread one per block, beside interior
+// ones, so that the CUs carry a similar mix of wall and interior work; with
+// lockstep the wall wavefronts fill blocks of their own.  Block b runs on XCD b % 8; the
 // interior items of a few contiguous bands of rows go to the blocks of one
 // XCD, neighbouring strips of a segment sharing a block.
 bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bool lockstep, bool xw_strips,
@@ -389,14 +388,14 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
     auto place = [&](const std::vector<Cand>& items, std::vector<std::pair<long long, lbm::WorkItem>>* out) {
         double total_cost = 0.0;
         for (const auto& it : items) total_cost += it.cost;
-        std::vector<std::vector<size_t>> band(NX);
+        std::vector<std::vector<size_t>> on_xcd(NX);   // item indices per XCD
         double acc = 0.0;
         for (size_t i = 0; i < items.size(); ++i) {
             const double mid = acc + 0.5 * items[i].cost;
             acc += items[i].cost;
             const int j = std::min(kBands - 1, int(mid / std::max(total_cost, 1e-300) * kBands));
             const int k = j % NX;
-            band[size_t(k)].push_back(i);
+            on_xcd[size_t(k)].push_back(i);
         }
         long long total_blocks = (long long)round_up(size_t(wall_blocks), NX);
         for (int k = 0; k < NX; ++k) {
@@ -412,16 +411,16 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
                 total_blocks = std::max(total_blocks, (blk / NX + 1) * NX);
             };
             if (lockstep) {
-                for (size_t i : band[size_t(k)])
+                for (size_t i : on_xcd[size_t(k)])
                     if (items[i].edge) put(items[i].w);
                 if (fill > 0) fill = PB;   // blocks of edge items hold nothing else
-                for (size_t i : band[size_t(k)])
+                for (size_t i : on_xcd[size_t(k)])
                     if (!items[i].edge) put(items[i].w);
             } else {
                 // edge items spread evenly through the band, so that no CU
                 // holds more than its share of their heavier rows
                 std::vector<size_t> e_i, r_i;
-                for (size_t i : band[size_t(k)]) (items[i].edge ? e_i : r_i).push_back(i);
+                for (size_t i : on_xcd[size_t(k)]) (items[i].edge ? e_i : r_i).push_back(i);
                 const size_t N = e_i.size() + r_i.size(), E = e_i.size();
                 size_t ie = 0, ir = 0;
                 for (size_t p = 0; p < N; ++p) {

@@ -887,7 +887,7 @@ __device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w,
 // ---------------------------------------------------------------------------
 // step kernel: one launch per time step.  The host lays the work list out
 // slot by slot (slot = block * Tuning::block_waves + wave) so that wall items
-// start first and each XCD's blocks cover one contiguous band of rows;
+// start first and each XCD's blocks cover a few contiguous bands of rows;
 // kind 2 marks an empty slot.
 // ---------------------------------------------------------------------------
 
