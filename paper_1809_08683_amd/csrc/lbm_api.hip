@@ -284,20 +284,16 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
         // pulls at x_f, x_ff along the inner normal and of its gradient
         // neighbours, the inversions).  A wavefront takes wall-row nodes 64
         // at a time, in chunks of whole passes that last about as long as an
-        // interior item.  The nodes of x-wall columns (one cache line per
-        // node and DF row) get the wavefronts their cost share of the slots
-        // asks for, at least one per CU while that leaves 16 or more nodes
-        // to each.
+        // interior item.  Where wall items also take x-wall columns (one
+        // cache line per node and DF row), each wavefront gets a single pass:
+        // the column gathers need many wavefronts in flight, and a one-pass
+        // wavefront still ends before the interior ones.
         constexpr double kWallCost = 12.0;
-        const double interior = double(total_cells) * lbm::STRIP_COLS;
-        const double frac = kWallCost * double(total_wall) / (kWallCost * double(total_wall) + interior);
-        long long nw = std::max<long long>((long long)std::llround(frac * double(capacity)), 1);
         bool columns = false;
         for (int k = 0; k < nc; ++k) columns = columns || (c->P[k].wall_x && !xw_strips);
         int chunk;
         if (columns) {
-            nw = std::max(nw, std::min<long long>(cus, (total_wall + 15) / 16));
-            chunk = int((total_wall + nw - 1) / nw);
+            chunk = lbm::REGION_SLOTS;
         } else {
             // whole passes of 64 nodes, as many as make a wall item about as
             // long as an interior item (a pass costs kWallCost * 64 / 60 rows)
