@@ -282,27 +282,21 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
     if (total_wall > 0) {
         // A wall node costs about kWallCost interior nodes (its own pull, the
         // pulls at x_f, x_ff along the inner normal and of its gradient
-        // neighbours, the inversions).  A wavefront takes wall-row nodes 64
-        // at a time, in chunks of whole passes that last about as long as an
-        // interior item.  Where wall items also take x-wall columns (one
-        // cache line per node and DF row), each wavefront gets a single pass:
-        // the column gathers need many wavefronts in flight, and a one-pass
-        // wavefront still ends before the interior ones.
-        constexpr double kWallCost = 12.0;
+        // neighbours, the inversions).  A wavefront takes wall nodes 64 at a
+        // time, in chunks of whole passes, as many as make a wall item last
+        // about as long as an interior item.  Where wall items also take
+        // x-wall columns (one cache line per node and DF row, gathered), a
+        // pass costs about kColumnFactor times more: the gathers need many
+        // wavefronts in flight (a 2048^2 FP64 cavity then gets one pass per
+        // wall wavefront).
+        constexpr double kWallCost = 12.0, kColumnFactor = 2.5;
         bool columns = false;
         for (int k = 0; k < nc; ++k) columns = columns || (c->P[k].wall_x && !xw_strips);
-        int chunk;
-        if (columns) {
-            chunk = lbm::REGION_SLOTS;
-        } else {
-            // whole passes of 64 nodes, as many as make a wall item about as
-            // long as an interior item (a pass costs kWallCost * 64 / 60 rows)
-            const double pass_rows = kWallCost * lbm::REGION_SLOTS / lbm::STRIP_COLS;
-            const double item_rows = (double(total_cells) + pass_rows * double(total_wall) / lbm::REGION_SLOTS) /
-                                     double(capacity);
-            const long long passes = std::max<long long>(1, std::llround(item_rows / pass_rows));
-            chunk = int(passes * lbm::REGION_SLOTS);
-        }
+        const double pass_rows = kWallCost * lbm::REGION_SLOTS / lbm::STRIP_COLS * (columns ? kColumnFactor : 1.0);
+        const double item_rows = (double(total_cells) + pass_rows * double(total_wall) / lbm::REGION_SLOTS) /
+                                 double(capacity);
+        const long long passes = std::max<long long>(1, std::llround(item_rows / pass_rows));
+        const int chunk = int(passes * lbm::REGION_SLOTS);
         for (int k = 0; k < nc; ++k)
             for (int b = 0; b < nwall[k]; b += chunk) wall.push_back({k, 1, b, 0, std::min(chunk, nwall[k] - b), 0});
     }
