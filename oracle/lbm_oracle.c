@@ -17,16 +17,21 @@
  *   - gradients in T.grad(rho) and X.grad(p): isotropic 9-point central
  *     difference at nodes off the walls; at wall nodes a second-order
  *     one-sided difference along a walled axis and a two-point central
- *     difference along an open axis; same time level as the collision;
+ *     difference along an open axis; same time level as the collision
+ *     (parity unpinned: no printed value fixes the stencil);
  *   - p inside X.grad(p) is p_EOS(rho, T);
  *   - corner nodes: bounce-back temporaries for every unknown DF, velocity
  *     and Dirichlet temperature of the x-wall (else of the y-wall),
- *     extrapolation along the inward diagonal;
+ *     extrapolation along the inward diagonal (parity unpinned);
  *   - the start state (t = 0) is m = m^eq - F_m/2, n = n^eq - Q_m/2 at every
  *     node, walls included; wall velocity/temperature apply from t = 1;
  *   - T = (E - |u|^2/2) / C_v for every equation of state (Sec. 2.2);
  *   - local rates: 1/s_p = mu(T)/(rho c_s^2) + 1/2 with the local rho, and
- *     1/sigma_j = 1/2 + lambda(T)/(kappa rho0 C_p) with lambda = C_p mu/Pr.
+ *     1/sigma_j = 1/2 + lambda(T)/(kappa rho0 C_p) with lambda = C_p mu/Pr;
+ *   - mean Nusselt number: trapezoid rule along the wall of
+ *     lambda(T_b) (-dT/dn) / (lambda0 (T_lo - T_hi)), with the second-order
+ *     one-sided difference (-3 T0 + 4 T1 - T2) / 2 (parity unpinned for the
+ *     stencil; Nu = 1 for pure conduction is pinned).
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, so
  * results do not depend on the compiler's fusion choices).
