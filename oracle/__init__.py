@@ -92,6 +92,7 @@ def _load():
         lib.orc_rates.argtypes = [vp, C.c_double, C.c_double, _D]
         lib.orc_matrices.argtypes = [vp] + [C.c_double] * 4 + [_D] * 6
         lib.orc_collide_node.argtypes = [vp] + [_D] * 9
+        lib.orc_gradient.argtypes = [vp, _D, C.c_int, C.c_int, _D, _D]
         _lib = lib
     return _lib
 
@@ -240,6 +241,13 @@ class Oracle:
         self.lib.orc_matrices(self.h, rho, ux, uy, T, *[_ptr(a) for a in (S, R, Tm, X, L, Y)])
         return dict(S=S.reshape(9, 9), R=R.reshape(9, 9), T=Tm.reshape(9, 2), X=X.reshape(9, 2),
                     L=L.reshape(9, 9), Y=Y.reshape(9, 9))
+
+    def gradient(self, phi, x, y):
+        """(d/dx, d/dy) of phi[ny, nx] at node (x, y), as used for grad(rho), grad(p)."""
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+        gx, gy = C.c_double(), C.c_double()
+        self.lib.orc_gradient(self.h, _ptr(phi), int(x), int(y), C.byref(gx), C.byref(gy))
+        return gx.value, gy.value
 
     def collide_node(self, f, g, grad):
         f = np.ascontiguousarray(f, dtype=np.float64)

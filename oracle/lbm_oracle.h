@@ -99,6 +99,9 @@ void orc_rates(const orc* o, double rho, double T, double rates[10]);
 void orc_matrices(const orc* o, double rho, double ux, double uy, double T,
                   double S[81], double R[81], double Tm[18], double X[18],
                   double L[81], double Y[81]);
+/* Gradient (d/dx, d/dy) at node (x, y) of a field phi[ny*nx] with the
+ * stencil the collision uses for grad(rho) and grad(p). */
+void orc_gradient(const orc* o, const double* phi, int x, int y, double* gx, double* gy);
 /* One collision of a node whose pre-collision DFs are f, g, with macros
  * computed from f, g as at an interior node, and the given gradients
  * grad = (drho/dx, drho/dy, dp/dx, dp/dy).  Also returns m, mbar, n, nbar. */
