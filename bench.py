@@ -147,22 +147,94 @@ def time_batch(steps, warmup, prec="f32"):
     return res
 
 
-def cpu_baseline(seconds_target=15.0):
-    """The FP64 CPU oracle (single thread, as written) on a bounded sample:
-    a 256 x 256 cavity (eps 0.6, Ra 1e5) stepped until ~15 s have passed."""
+def batch_accuracy(steps, prec="f32"):
+    """Per-case mean Nusselt number of the batched sweep in `prec` against the
+    same sweep stepped in FP64 on the GPU, after `steps` steps from the same
+    start, with the a-priori flag of each case (no viscosity keeps the paired
+    relaxation rates below 1.75 at both walls) and the Rayleigh number the
+    case runs at (Ra_eff, where its viscosity was moved into that window)."""
+    from paper_1809_08683_amd import inputs, lbm
+
+    runs = {}
+    for pr in (prec, "f64"):
+        cases = inputs.batch_cases(seed=2, n=64, prec=pr)
+        b = lbm.Batch(cases)
+        for k, c in enumerate(cases):
+            b.init(k, rho=1.0 + 1e-6 * inputs.noise(3 + k, c["nx"] * c["ny"]).reshape(c["ny"], c["nx"]))
+        done = 0
+        while done < steps:
+            n = min(1000, steps - done)
+            b.step(n, allow_diverged=True)
+            done += n
+        flags = b.flags()
+        nu = [None if flags[k] else b.nusselt(k, 0) for k in range(len(cases))]
+        runs[pr] = (cases, flags, nu)
+        b.close()
+        log(f"bench: batch accuracy {pr}: {steps} steps, {sum(flags)} cases diverged")
+    cases, f_lo, nu_lo = runs[prec]
+    _, f_64, nu_64 = runs["f64"]
+    rows, errs = [], []
+    for k, c in enumerate(cases):
+        err = None
+        if nu_lo[k] is not None and nu_64[k] is not None:
+            err = abs(nu_lo[k] - nu_64[k]) / abs(nu_64[k])
+            errs.append(err)
+        rows.append([k, c["nx"], float(f"{c['Ra']:.4g}"), float(f"{c['Ra_eff']:.4g}"), round(c["eps"], 4), c["Pr"],
+                     round(c["nu0"], 5), bool(c["window_empty"]),
+                     None if nu_64[k] is None else round(nu_64[k], 6),
+                     None if err is None else float(f"{err:.3g}"), bool(f_lo[k]), bool(f_64[k])])
+    return {
+        "steps": steps,
+        "prec": prec,
+        "columns": ["case", "N", "Ra", "Ra_eff", "eps", "Pr", "nu0", "flagged_a_priori", "Nu_f64",
+                    f"Nu_rel_err_{prec}_vs_f64", f"diverged_{prec}", "diverged_f64"],
+        "cases": rows,
+        "flagged_a_priori": int(sum(r[7] for r in rows)),
+        "max_Nu_rel_err": None if not errs else float(f"{max(errs):.3g}"),
+        "cases_within_0.5pct": int(sum(e <= 5e-3 for e in errs)),
+        "cases_compared": len(errs),
+    }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seconds_target=12.0):
+    """The FP64 CPU oracle as written, on a bounded sample: a 256 x 256 cavity
+    (eps 0.6, Ra 1e5) stepped for about `seconds_target` seconds on one host
+    thread and again on all the host threads this process may use (its node
+    loops run under OpenMP with bitwise the serial result)."""
     import oracle
     from paper_1809_08683_amd import inputs
 
-    c = inputs.cavity(N=256, Ra=1e5, prec="f64", noise_seed=1)
-    o = oracle.Oracle(c).init(**c["init"])
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds_target:
-        o.step(5)
-        steps += 5
-    dt = time.perf_counter() - t0
-    return {"value": 256 * 256 * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"256x256 cavity (eps 0.6, Ra 1e5), {steps} steps, FP64, one host thread, {dt:.1f} s"}
+    def run(threads):
+        c = inputs.cavity(N=256, Ra=1e5, prec="f64", noise_seed=1)
+        o = oracle.Oracle(c).set_threads(threads).init(**c["init"])
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds_target:
+            o.step(5)
+            steps += 5
+        dt = time.perf_counter() - t0
+        return 256 * 256 * steps / dt / 1e6, steps, dt
+
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = max(1, min(avail, int(os.environ.get("OMP_NUM_THREADS") or avail)))
+    v1, s1, t1 = run(1)
+    vn, sn, tn = run(threads)
+    return {"value": round(vn, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"256x256 cavity (eps 0.6, Ra 1e5), FP64: {sn} steps in {tn:.1f} s on {threads} threads; "
+                      f"{s1} steps in {t1:.1f} s on one thread",
+            "value_1core": round(v1, 3), "nproc": os.cpu_count(), "threads_available": avail,
+            "cpu_model": _cpu_model()}
 
 
 def main():
@@ -175,6 +247,8 @@ def main():
     ap.add_argument("--seg-rows", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-acc-steps", type=int, default=20000,
+                    help="steps of the per-case FP32-vs-FP64 Nusselt comparison of the batched sweep (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: runs on one GPU only (a multi-GPU slab decomposition is designed "
@@ -200,6 +274,9 @@ def main():
         log("bench: 64-cavity batch f32: warmup 20, timed 100 steps")
         batch = time_batch(100, 20)
         log(f"bench: batch: {json.dumps(batch)}")
+        if args.batch_acc_steps > 0:
+            batch["accuracy"] = batch_accuracy(args.batch_acc_steps)
+            log(f"bench: batch accuracy: {json.dumps(batch['accuracy'])}")
     copy_gbs, _ = lbm.copy_bandwidth(1 << 30, iters=20)
     log(f"bench: device copy bandwidth {copy_gbs:.0f} GB/s")
 

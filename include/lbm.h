@@ -170,7 +170,11 @@ lbm_status lbm_nusselt(lbm_ctx* ctx, int side, double* nu);
  * fixed reduction order). */
 lbm_status lbm_totals(lbm_ctx* ctx, double* mass, double* momx, double* momy, double* energy);
 
-/* Checkpoint: raw DF state plus time; bytes = lbm_state_bytes(ctx). */
+/* Checkpoint: a format tag, t, the case count, a record per case (nx, ny,
+ * precision, row pitch, buffer sizes), then the raw DF state and macros;
+ * bytes = lbm_state_bytes(ctx).  lbm_load returns LBM_EINVAL, leaving the
+ * context unchanged, if the tag, the case count or any case record differs
+ * from the context's own. */
 size_t     lbm_state_bytes(const lbm_ctx* ctx);
 lbm_status lbm_save(lbm_ctx* ctx, void* host, size_t bytes);
 lbm_status lbm_load(lbm_ctx* ctx, const void* host, size_t bytes);

@@ -25,11 +25,11 @@ VISC = {"const": 0, "linear": 1, "sutherland": 2}
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle (gcc, FP64, no FMA contraction)."""
+    """Compile the oracle (gcc, FP64, no FMA contraction, OpenMP node loops)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+            ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-Wall",
              "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -77,6 +77,7 @@ def _load():
         lib.orc_step.argtypes = [vp, C.c_longlong]
         lib.orc_time.argtypes = [vp]
         lib.orc_time.restype = C.c_longlong
+        lib.orc_set_threads.argtypes = [vp, C.c_int]
         lib.orc_macros.argtypes = [vp, _D, _D, _D, _D, _D]
         lib.orc_get_df.argtypes = [vp, _D, _D]
         lib.orc_nusselt.argtypes = [vp, C.c_int, _D]
@@ -173,6 +174,11 @@ class Oracle:
         conv = [None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
                 for a in (rho, ux, uy, T)]
         self._check(self.lib.orc_init(self.h, *[_ptr(a) for a in conv]), "orc_init")
+        return self
+
+    def set_threads(self, n: int):
+        """OpenMP threads of the node loops (the result does not depend on it)."""
+        self.lib.orc_set_threads(self.h, int(n))
         return self
 
     def step(self, n: int = 1):

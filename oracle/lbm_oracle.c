@@ -46,6 +46,11 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* The node loops of a step are independent per node (every node reads the
+ * previous arrays and writes only its own entries), so running them on
+ * several OpenMP threads gives bitwise the serial result. */
+#define ORC_PARALLEL_ROWS _Pragma("omp parallel for schedule(static) num_threads(o->threads) if(o->threads > 1)")
+
 struct orc {
     orc_params P;
     orc_derived D;
@@ -57,6 +62,7 @@ struct orc {
     double *rho, *ux, *uy, *T, *rhoE, *p;  /* macros at t */
     long long t;
     int ready;
+    int threads;               /* OpenMP threads of the node loops (1: serial) */
     char err[256];
 };
 
@@ -693,6 +699,7 @@ int orc_create(const orc_params* p, orc** out)
         *out = o; return fail(o, -1, "invalid parameter");
     }
 
+    o->threads = 1;
     orc_lattice(o->ex, o->ey, o->w);
     for (int q = 0; q < 9; ++q)
         for (int r = 0; r < 9; ++r)
@@ -760,6 +767,8 @@ void orc_destroy(orc* o)
 
 long long orc_time(const orc* o) { return o->t; }
 
+void orc_set_threads(orc* o, int n) { o->threads = n > 0 ? n : 1; }
+
 static int check_state(orc* o)
 {
     size_t nn = (size_t)o->P.nx * o->P.ny;
@@ -774,6 +783,7 @@ static int check_state(orc* o)
 int orc_init(orc* o, const double* rho, const double* ux, const double* uy, const double* T)
 {
     const int nx = o->P.nx, ny = o->P.ny;
+    ORC_PARALLEL_ROWS
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int i = y * nx + x;
@@ -832,6 +842,7 @@ static int one_step(orc* o)
     const size_t nn = (size_t)nx * ny;
 
     /* 1. collision at time t of every node, with gradients at time t */
+    ORC_PARALLEL_ROWS
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int i = y * nx + x;
@@ -846,6 +857,7 @@ static int one_step(orc* o)
 
     /* 2. streaming (eqs. LBE.u.s, LBE.T.s); DFs whose source lies outside a
      *    wall take the bounce-back temporaries (eqs. BB.f, BB.g) */
+    ORC_PARALLEL_ROWS
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int i = y * nx + x;
@@ -865,6 +877,7 @@ static int one_step(orc* o)
 
     /* 3. macros at t+1: off-wall nodes from their DFs; wall nodes from the
      *    temporaries (rho; rho*E when adiabatic) and the prescribed values */
+    ORC_PARALLEL_ROWS
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int i = y * nx + x;
@@ -900,6 +913,8 @@ static int one_step(orc* o)
      *    every extrapolation reads streamed values. */
     int any_wall = o->P.side_wall[0] || o->P.side_wall[2];
     if (any_wall) {
+        int singular = 0;
+        ORC_PARALLEL_ROWS
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 if (!is_wall(o, x, y)) continue;
@@ -931,10 +946,18 @@ static int one_step(orc* o)
                     IL[k] = id - 0.5 * L[k];
                 }
                 double mneq[9], YZ[9], rhs[9], nneq[9];
-                if (solve9(IS, Zm, mneq)) return fail(o, -4, "singular I - S/2");
+                if (solve9(IS, Zm, mneq)) {
+#pragma omp atomic write
+                    singular = 1;
+                    continue;
+                }
                 matvec9(Y, Zm, YZ);
                 for (int q = 0; q < 9; ++q) rhs[q] = Zn[q] - 0.5 * YZ[q];
-                if (solve9(IL, rhs, nneq)) return fail(o, -4, "singular I - L/2");
+                if (solve9(IL, rhs, nneq)) {
+#pragma omp atomic write
+                    singular = 2;
+                    continue;
+                }
                 double meq[9], Fm[9], neq[9], Qm[9], m[9], n[9];
                 orc_meq(o, s.rho, s.ux, s.uy, s.eta, meq);
                 orc_fm(o, s.Fx, s.Fy, s.ux, s.uy, Fm);
@@ -947,6 +970,7 @@ static int one_step(orc* o)
                 matvec9(o->Minv, m, o->fs + (size_t)i * 9);
                 matvec9(o->Minv, n, o->gs + (size_t)i * 9);
             }
+        if (singular) return fail(o, -4, singular == 1 ? "singular I - S/2" : "singular I - L/2");
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 if (!is_wall(o, x, y)) continue;

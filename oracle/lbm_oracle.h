@@ -74,6 +74,9 @@ int  orc_init(orc* o, const double* rho, const double* ux, const double* uy, con
 /* n steps; returns -4 on divergence (non-finite, rho <= 0 or T <= 0). */
 int  orc_step(orc* o, long long n);
 long long orc_time(const orc* o);
+/* OpenMP threads for the node loops of init and step (default 1).  The
+ * result is bitwise the same for any count. */
+void orc_set_threads(orc* o, int n);
 /* Macroscopic fields at the current time (wall nodes report their
  * prescribed / derived values).  Any pointer may be NULL. */
 int  orc_macros(const orc* o, double* rho, double* ux, double* uy, double* T, double* p);

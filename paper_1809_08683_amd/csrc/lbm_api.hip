@@ -87,6 +87,7 @@ struct lbm_ctx {
     std::vector<void*> allocs;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = 0;                      // device current at creation
     int parity = 0;
     long long t = 0;
     std::string err;
@@ -466,6 +467,7 @@ lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* 
         if (st != LBM_OK) return st;
         if (opt[k].prec != c->prec) return fail(c, LBM_EINVAL, "all cases of a batch share one precision");
     }
+    HIP_TRY(c, hipGetDevice(&c->device));
     // device memory
     size_t total = 0;
     std::vector<Layout> L(ncases);
@@ -503,7 +505,7 @@ lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* 
         off += L[k].total;
     }
     int cus = 0;
-    HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
+    HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
     if (!build_work(c, opt[0].seg_rows, cus, lbm::step_blocks_per_cu(c->prec),
                     lbm::step_block_waves(c->prec), lbm::step_lockstep(c->prec) != 0,
                     lbm::step_xwall_in_strips(c->prec) != 0, lbm::step_xwall_cost(c->prec)))
@@ -547,6 +549,25 @@ lbm_status read_flags(lbm_ctx* c, std::vector<int>& flags)
         HIP_TRY(c, hipMemcpyAsync(&flags[k], c->P[k].flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
+}
+
+// Checkpoint layout: an 8-byte format tag, t and the case count, one
+// CkptCase record per case, then per case the current DF buffer and the
+// macro array.  lbm_load accepts a checkpoint only if every record equals the
+// context's own.
+constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '2'};
+constexpr size_t kCkptHeader = 24;
+struct CkptCase {
+    int nx, ny, prec, pitch;
+    long long buf_bytes, macro_bytes;
+};
+constexpr size_t kCkptCase = sizeof(CkptCase);
+static_assert(kCkptCase == 32, "checkpoint case record is 32 bytes");
+
+CkptCase ckpt_case(const lbm_ctx* c, size_t k)
+{
+    const auto& h = c->H[k];
+    return CkptCase{h.nx, h.ny, c->prec, h.L.pitch, (long long)h.L.buf_bytes, (long long)h.L.macro_bytes};
 }
 
 lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t e0, hipEvent_t e1)
@@ -751,7 +772,7 @@ lbm_status lbm_batch_flags(lbm_ctx* c, int* diverged)
 size_t lbm_state_bytes(const lbm_ctx* c)
 {
     if (!c) return 0;
-    size_t s = 16;
+    size_t s = kCkptHeader + c->H.size() * kCkptCase;
     for (const auto& h : c->H) s += h.L.buf_bytes + h.L.macro_bytes;
     return s;
 }
@@ -763,8 +784,14 @@ lbm_status lbm_save(lbm_ctx* c, void* host, size_t bytes)
     if (!host || bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer smaller than lbm_state_bytes");
     char* o = static_cast<char*>(host);
     const long long hdr[2] = {c->t, (long long)c->P.size()};
-    std::memcpy(o, hdr, 16);
-    o += 16;
+    std::memcpy(o, kCkptMagic, 8);
+    std::memcpy(o + 8, hdr, 16);
+    o += kCkptHeader;
+    for (size_t k = 0; k < c->H.size(); ++k) {
+        const CkptCase cc = ckpt_case(c, k);
+        std::memcpy(o, &cc, kCkptCase);
+        o += kCkptCase;
+    }
     for (size_t k = 0; k < c->H.size(); ++k) {
         const auto& h = c->H[k];
         HIP_TRY(c, hipMemcpyAsync(o, h.base + c->parity * h.L.buf_bytes, h.L.buf_bytes, hipMemcpyDeviceToHost, c->stream));
@@ -780,12 +807,23 @@ lbm_status lbm_load(lbm_ctx* c, const void* host, size_t bytes)
 {
     lbm_status st = check_ctx(c);
     if (st != LBM_OK) return st;
-    if (!host || bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer smaller than lbm_state_bytes");
+    if (!host || bytes < kCkptHeader) return fail(c, LBM_EINVAL, "buffer smaller than a checkpoint header");
     const char* o = static_cast<const char*>(host);
+    if (std::memcmp(o, kCkptMagic, 8) != 0) return fail(c, LBM_EINVAL, "not a checkpoint of this library (format tag)");
     long long hdr[2];
-    std::memcpy(hdr, o, 16);
+    std::memcpy(hdr, o + 8, 16);
     if (hdr[1] != (long long)c->P.size()) return fail(c, LBM_EINVAL, "checkpoint has a different number of cases");
-    o += 16;
+    if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer smaller than lbm_state_bytes");
+    o += kCkptHeader;
+    for (size_t k = 0; k < c->H.size(); ++k) {
+        CkptCase cc;
+        std::memcpy(&cc, o, kCkptCase);
+        o += kCkptCase;
+        const CkptCase mine = ckpt_case(c, k);
+        if (std::memcmp(&cc, &mine, kCkptCase) != 0)
+            return fail(c, LBM_EINVAL, "checkpoint case " + std::to_string(k) +
+                                           " differs in grid, precision or layout from this context");
+    }
     for (size_t k = 0; k < c->H.size(); ++k) {
         auto& h = c->H[k];
         HIP_TRY(c, hipMemcpyAsync(h.base + c->parity * h.L.buf_bytes, o, h.L.buf_bytes, hipMemcpyHostToDevice, c->stream));

@@ -194,6 +194,8 @@ def batch_cases(seed=2, n=64, Ma=0.05, nu_min=0.1, smax=1.75, prec="f32") -> lis
         c["Ra_eff"] = Ra
         lo, hi = stable_nu0_window(eps, Pr, smax)
         lo = max(lo, nu_min)
+        c["nu0_window"] = (lo, hi)
+        c["window_empty"] = lo > hi      # flagged before any step: may diverge
         nu = c["nu0"] if lo <= hi else math.sqrt(lo * hi)
         nu = min(max(nu, lo), hi) if lo <= hi else nu
         if nu != c["nu0"]:

@@ -129,8 +129,8 @@ def test_batch_divergence_flags_only_that_case():
 def test_batch_sweep_configuration():
     """The uneven sweep of 64 cavities (N in {128..1024}, Ra log-uniform in
     [1e3, 1e8], eps in [0.1, 0.6], Pr in {0.71, 1, 7}), FP32, in one batch:
-    no case diverges in 10 steps, every case keeps its mass, and sampled
-    cases agree with the oracle."""
+    no case diverges in 10 steps, every case keeps its mass, and one case of
+    every size (1024^2 included) agrees with the oracle."""
     cases = inputs.batch_cases(seed=2, n=64, prec="f32")
     nodes = sum(c["nx"] * c["ny"] for c in cases)
     print(f"64-case sweep: {nodes} nodes", flush=True)
@@ -144,7 +144,8 @@ def test_batch_sweep_configuration():
         m1 = b.totals(k)[0]
         assert abs(m1 - m0[k]) / m0[k] < 1e-6, (k, m0[k], m1)
     sizes = [c["nx"] for c in cases]
-    picks = [sizes.index(n) for n in (128, 256, 512) if n in sizes]
+    picks = [sizes.index(n) for n in (128, 256, 512, 1024) if n in sizes]
+    assert len(picks) == 4
     for k in picks:
         c = cases[k]
         rho0 = 1.0 + 1e-6 * inputs.noise(3 + k, c["nx"] * c["ny"]).reshape(c["ny"], c["nx"])

@@ -263,6 +263,26 @@ def test_deterministic_and_checkpoint():
         assert np.array_equal(a[k], m[k])
 
 
+def test_checkpoint_from_another_layout_is_rejected():
+    """lbm_load checks the format tag and every case record (grid,
+    precision, pitch, buffer sizes) and leaves the context unchanged."""
+    c = dict(_cavity(40, ny=30), prec="f32")
+    f = inputs.random_fields(c, 4, du=0.01, drho=0.02, dT=0.02)
+    blob = lbm.Context(c).init(**f).step(5).save()
+    for other in (dict(c, prec="f64"), dict(_cavity(41, ny=30), prec="f32"), dict(_cavity(40, ny=31), prec="f32")):
+        g = lbm.Context(other).init()
+        padded = blob + bytes(max(0, g.lib.lbm_state_bytes(g.h) - len(blob)))
+        with pytest.raises(lbm.LBMError) as ei:
+            g.load(padded)
+        assert ei.value.status == lbm.EINVAL
+        assert g.time == 0
+    bad = bytearray(blob)
+    bad[0:8] = b"NOTACKPT"
+    with pytest.raises(lbm.LBMError):
+        lbm.Context(c).load(bytes(bad))
+    assert lbm.Context(c).load(blob).time == 5
+
+
 def test_torch_workspace_and_stream():
     import torch
     c = dict(_cavity(40, ny=30), prec="f64")

@@ -271,3 +271,21 @@ def test_nusselt_of_pure_conduction():
     o.step(8000)
     assert o.nusselt(0) == pytest.approx(1.0, abs=1e-6)
     assert o.nusselt(1) == pytest.approx(1.0, abs=1e-6)
+
+
+def test_threaded_oracle_is_bitwise_serial():
+    """The oracle's node loops on several OpenMP threads give exactly the
+    serial state (every node writes only its own entries), walls, corners,
+    gravity and both thermal wall kinds included."""
+    c = inputs.cavity(N=24, Ra=1e4, eps=0.3, nu0=0.1, prec="f64")
+    c["force"] = (0.0, -1e-4)
+    f = inputs.random_fields(c, 12, du=0.01, drho=0.02, dT=0.02)
+    a = oracle.Oracle(c).init(**f).step(40)
+    b = oracle.Oracle(c).set_threads(4)
+    b.init(**f).step(40)
+    fa, ga = a.df()
+    fb, gb = b.df()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    ma, mb = a.macros(), b.macros()
+    for k in ma:
+        assert np.array_equal(ma[k], mb[k])
