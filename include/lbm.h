@@ -198,6 +198,18 @@ lbm_status lbm_case_macros(lbm_ctx* ctx, int case_id, double* rho, double* ux, d
 lbm_status lbm_case_nusselt(lbm_ctx* ctx, int case_id, int side, double* nu);
 lbm_status lbm_case_totals(lbm_ctx* ctx, int case_id, double* mass, double* momx, double* momy,
                            double* energy);
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid hipMalloc): as lbm_case_init,
+ * but the four host fields are staged in a library-owned static device
+ * array instead of a per-call allocation.  The array holds 4 x 2^20 doubles
+ * (32 MiB), one copy per GPU, kept until the process ends; grids of more
+ * than 2^20 nodes are rejected with LBM_EINVAL (use lbm_case_init).  Calls no
+ * hipMalloc/hipFree.  Every call on one GPU shares that array: calls that
+ * overlap in time on one GPU (from several threads) race.  Synchronises the
+ * context stream before returning. */
+lbm_status lbm_case_init_static(lbm_ctx* ctx, int case_id, const double* rho, const double* ux,
+                                const double* uy, const double* T);
+
 /* Divergence flag of each case (1: diverged) after the last step call. */
 lbm_status lbm_batch_flags(lbm_ctx* ctx, int* diverged);
 

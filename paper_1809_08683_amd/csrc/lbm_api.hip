@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -594,6 +595,53 @@ lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t e0, hipEvent_t e1)
 
 }  // namespace
 
+// ---- staging scratch of the allocation-free initialisation ---------------
+// lbm_case_init stages the four host fields in a device buffer it allocates
+// per call.  lbm_case_init_static stages them in this file-scope array
+// instead: one copy per GPU, held until the process ends.  Host code must
+// not pass the array's name to a kernel or a copy (on the host it is only a
+// stand-in); it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+constexpr long long kInitScratchNodes = 1LL << 20;   // 4 fields x 2^20 doubles = 32 MiB
+static __device__ __align__(256) double scratch[4 * kInitScratchNodes];
+
+__global__ void fill_doubles(double* __restrict__ p, long long n, double v)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void clear_flag(int* flag) { *flag = 0; }
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the context's device (looked up on first use
+// there, with that device current).
+lbm_status scratch_on_device(lbm_ctx* c, double** out)
+{
+    if (c->device < 0 || c->device >= kMaxDevices) return fail(c, LBM_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[c->device]) {
+        int prev = 0;
+        HIP_TRY(c, hipGetDevice(&prev));
+        if (prev != c->device) HIP_TRY(c, hipSetDevice(c->device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != c->device) (void)hipSetDevice(prev);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(c, LBM_EDEVICE, "hipGetSymbolAddress(scratch) returned no address");
+        g_scratch[c->device] = static_cast<double*>(p);
+    }
+    *out = g_scratch[c->device];
+    return LBM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t lbm_workspace_bytes(int nx, int ny, int prec)
@@ -669,6 +717,46 @@ lbm_status lbm_case_init(lbm_ctx* c, int k, const double* rho, const double* ux,
 lbm_status lbm_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* T)
 {
     return lbm_case_init(c, 0, rho, ux, uy, T);
+}
+
+lbm_status lbm_case_init_static(lbm_ctx* c, int k, const double* rho, const double* ux, const double* uy,
+                                const double* T)
+{
+    lbm_status st = check_case(c, k);
+    if (st != LBM_OK) return st;
+    const auto& P = c->P[k];
+    const long long nn = (long long)P.nx * P.ny;
+    if (nn > kInitScratchNodes)
+        return fail(c, LBM_EINVAL, "grid of " + std::to_string(nn) + " nodes exceeds the static init scratch (" +
+                                       std::to_string(kInitScratchNodes) + " nodes); use lbm_case_init");
+    const double* src[4] = {rho, ux, uy, T};
+    for (long long i = 0; i < nn; ++i) {
+        const double r = rho ? rho[i] : P.cd.rho0, t = T ? T[i] : P.cd.T0;
+        if (!(r > 0) || !(t > 0) || !std::isfinite(r) || !std::isfinite(t) || (ux && !std::isfinite(ux[i])) ||
+            (uy && !std::isfinite(uy[i])))
+            return fail(c, LBM_EINVAL, "initial fields must be finite with rho > 0 and T > 0");
+    }
+    double* d = nullptr;
+    st = scratch_on_device(c, &d);
+    if (st != LBM_OK) return st;
+    const double dflt[4] = {P.cd.rho0, 0.0, 0.0, P.cd.T0};
+    for (int f = 0; f < 4; ++f) {
+        if (src[f]) {
+            HIP_TRY(c, hipMemcpyAsync(d + f * nn, src[f], size_t(nn) * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        } else {
+            hipLaunchKernelGGL(fill_doubles, dim3(unsigned(std::min<long long>((nn + 255) / 256, 4096))), dim3(256), 0,
+                               c->stream, d + f * nn, nn, dflt[f]);
+            HIP_TRY(c, hipGetLastError());
+        }
+    }
+    hipLaunchKernelGGL(clear_flag, dim3(1), dim3(1), 0, c->stream, P.flag);
+    HIP_TRY(c, hipGetLastError());
+    const int rc = lbm::launch_init(c->prec, c->d_P, k, nn, d, c->parity, c->stream);
+    if (rc != 0) return hip_fail(c, hipError_t(rc), "init launch");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->H[k].inited = true;
+    if (c->P.size() == 1) c->t = 0;
+    return LBM_OK;
 }
 
 lbm_status lbm_step(lbm_ctx* c, long long n)

@@ -102,6 +102,7 @@ def load_library():
                               _D, _D, C.POINTER(Relax), C.POINTER(Boundary), C.POINTER(Options), cp], C.c_int),
         "lbm_batch_size": ([vp], C.c_int),
         "lbm_case_init": ([vp, C.c_int, _D, _D, _D, _D], C.c_int),
+        "lbm_case_init_static": ([vp, C.c_int, _D, _D, _D, _D], C.c_int),
         "lbm_case_macros": ([vp, C.c_int, _D, _D, _D, _D, _D], C.c_int),
         "lbm_case_nusselt": ([vp, C.c_int, C.c_int, _D], C.c_int),
         "lbm_case_totals": ([vp, C.c_int, _D, _D, _D, _D], C.c_int),
@@ -122,7 +123,7 @@ def exported_symbols():
     return ["lbm_create", "lbm_workspace_bytes", "lbm_create_ex", "lbm_init", "lbm_step",
             "lbm_step_timed", "lbm_macros", "lbm_nusselt", "lbm_totals", "lbm_state_bytes",
             "lbm_save", "lbm_load", "lbm_time", "lbm_last_error", "lbm_destroy",
-            "lbm_batch_create", "lbm_batch_size", "lbm_case_init", "lbm_case_macros",
+            "lbm_batch_create", "lbm_batch_size", "lbm_case_init", "lbm_case_init_static", "lbm_case_macros",
             "lbm_case_nusselt", "lbm_case_totals", "lbm_batch_flags", "lbm_work_items",
             "lbm_copy_bandwidth"]
 
@@ -264,6 +265,17 @@ class Context(_Base):
             if a is not None and a.size != self.nx * self.ny:
                 raise ValueError("initial field has the wrong size")
         self._check(self.lib.lbm_init(self.h, *[_ptr(a) for a in arrs]), "lbm_init")
+        return self
+
+    def init_static(self, rho=None, ux=None, uy=None, T=None):
+        """As init, through the entry point that stages the fields in the
+        library's static device scratch (no device allocation)."""
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+                for a in (rho, ux, uy, T)]
+        for a in arrs:
+            if a is not None and a.size != self.nx * self.ny:
+                raise ValueError("initial field has the wrong size")
+        self._check(self.lib.lbm_case_init_static(self.h, 0, *[_ptr(a) for a in arrs]), "lbm_case_init_static")
         return self
 
     def macros(self) -> dict:
