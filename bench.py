@@ -65,14 +65,11 @@ def measured_traffic():
     return None
 
 
-def time_path(case, prec, steps, warmup, seg_rows=0):
+def _timed(ctx, nodes, prec, steps, warmup):
+    """Warm-up, then `steps` timed steps (HIP events on the launch stream and
+    the host clock around them)."""
     import torch
-    from paper_1809_08683_amd import lbm
 
-    c = dict(case, prec=prec)
-    stream = torch.cuda.Stream()
-    ctx = lbm.Context(c, stream=stream, seg_rows=seg_rows)
-    ctx.init(**c["init"])
     # The 2048^2 Ra = 1e8 cavity leaves the stable range of the scheme
     # between steps 1000 and 2000 from rest (its buoyancy velocity passes
     # Mach 0.25); the cost of a step does not depend on the values, so a
@@ -92,7 +89,6 @@ def time_path(case, prec, steps, warmup, seg_rows=0):
     if diverged_at:
         log(f"bench: {prec}: the lattice state diverged during the {diverged_at} "
             f"(the timing covers complete steps)")
-    nodes = c["nx"] * c["ny"]
     per_step_kernel_s = kernel_ms * 1e-3 / steps
     res = {
         "mlups": nodes * steps / wall_s / 1e6,
@@ -105,6 +101,32 @@ def time_path(case, prec, steps, warmup, seg_rows=0):
         "state_diverged": diverged_at,
     }
     res["frac_hbm"] = res["achieved_GBs"] / PEAK_HBM_GBS
+    return res
+
+
+def time_path(case, prec, steps, warmup, seg_rows=0, tune=True):
+    """Times the step in the default launch configuration, then in the one
+    the autotuner picks (its cache file, or trials on this context when the
+    cache has no entry), from the same start state."""
+    import torch
+    from paper_1809_08683_amd import lbm
+
+    c = dict(case, prec=prec)
+    stream = torch.cuda.Stream()
+    ctx = lbm.Context(c, stream=stream, seg_rows=seg_rows)
+    nodes = c["nx"] * c["ny"]
+    ctx.init(**c["init"])
+    res = _timed(ctx, nodes, prec, steps, warmup)
+    if tune:
+        ctx.init(**c["init"])
+        t = ctx.autotune(trial_steps=100)
+        log(f"bench: {prec}: launch configuration {t}")
+        ctx.init(**c["init"])
+        tuned = _timed(ctx, nodes, prec, steps, warmup)
+        default = res
+        res = dict(tuned)
+        res["tune"] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in t.items()}
+        res["default_config"] = {k: default[k] for k in ("mlups", "ms_per_step", "kernel_ms_per_step", "frac_hbm")}
     ctx.close()
     return res
 
@@ -119,15 +141,30 @@ def time_batch(steps, warmup, prec="f32"):
     nodes = sum(c["nx"] * c["ny"] for c in cases)
     stream = torch.cuda.Stream()
     b = lbm.Batch(cases, stream=stream)
-    for k, c in enumerate(cases):
-        b.init(k, rho=1.0 + 1e-6 * inputs.noise(3 + k, c["nx"] * c["ny"]).reshape(c["ny"], c["nx"]))
-    if warmup:
-        b.step(warmup, allow_diverged=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kernel_ms = b.step_timed(steps, allow_diverged=True)
-    torch.cuda.synchronize()
-    wall_s = time.perf_counter() - t0
+
+    def start():
+        for k, c in enumerate(cases):
+            b.init(k, rho=1.0 + 1e-6 * inputs.noise(3 + k, c["nx"] * c["ny"]).reshape(c["ny"], c["nx"]))
+
+    def run(graph):
+        start()
+        if warmup:
+            b.step(warmup, allow_diverged=True)
+        if graph:                       # capture the graph of `steps` launches outside the timed region
+            b.step_ex(steps, graph=True, allow_diverged=True)
+            start()
+            b.step(warmup, allow_diverged=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = b.step_ex(steps, graph=graph, allow_diverged=True)
+        torch.cuda.synchronize()
+        return ms, time.perf_counter() - t0
+
+    default_ms, default_wall = run(False)
+    start()
+    tune = b.autotune(trial_steps=20)
+    log(f"bench: batch launch configuration {tune}")
+    kernel_ms, wall_s = run(True)
     flags = b.flags()
     per_step_s = kernel_ms * 1e-3 / steps
     res = {
@@ -141,6 +178,12 @@ def time_batch(steps, warmup, prec="f32"):
         "achieved_GBs": BYTES_PER_NODE[prec] * nodes / per_step_s / 1e9,
         "diverged_cases": int(sum(flags)),
         "work_items": b.work_items,
+        "stepping": "launch configuration from the autotuner, steps replayed as one captured HIP graph",
+        "tune": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in tune.items()},
+        "default_config": {"mlups": nodes * steps / default_wall / 1e6,
+                           "kernel_mlups": nodes / (default_ms * 1e-3 / steps) / 1e6,
+                           "frac_hbm": BYTES_PER_NODE[prec] * nodes / (default_ms * 1e-3 / steps) / 1e9 / PEAK_HBM_GBS,
+                           "stepping": "default configuration, one launch per step"},
     }
     res["frac_hbm"] = res["achieved_GBs"] / PEAK_HBM_GBS
     b.close()
@@ -245,6 +288,7 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--paths", default="f32,f16s,f32g16,f64")
     ap.add_argument("--seg-rows", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="time the default launch configuration only")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-acc-steps", type=int, default=20000,
@@ -267,7 +311,7 @@ def main():
     paths = {}
     for prec in args.paths.split(","):
         log(f"bench: {args.n}^2 cavity {prec}: warmup {args.warmup}, timed {args.steps} steps")
-        paths[prec] = time_path(case, prec, args.steps, args.warmup, args.seg_rows)
+        paths[prec] = time_path(case, prec, args.steps, args.warmup, args.seg_rows, tune=not args.no_tune)
         log(f"bench: {prec}: {json.dumps(paths[prec])}")
     batch = None
     if not args.no_batch:

@@ -141,8 +141,12 @@ lbm_status lbm_create_ex(int nx, int ny, const lbm_eos* eos, double Pr, double g
                          lbm_ctx** out);
 
 /* Initial state (t = 0) from host macroscopic fields: at every node, walls
- * included, m = m^eq - F_m/2 and n = n^eq - Q_m/2 (zero non-equilibrium
- * part), with E = C_v T + |u|^2/2.  NULL fields mean rho0, 0, 0, T0.
+ * included, the decomposition of eq. decompose (Sec. 3.2) with a zero
+ * non-equilibrium part, m = m^eq - F_m/2 and n = n^eq - Q_m/2, with
+ * E = C_v T + |u|^2/2 (Sec. 2.2); the runs of Secs. 4.1-4.3 start from rest
+ * at rho0, T0, which NULL fields give (rho0, 0, 0, T0).  Wall velocities and
+ * temperatures act from t = 1 (Sec. 4.3: walls changed abruptly).  Layout
+ * [ny][nx], caller-owned.  LBM_EINVAL for non-finite values or rho, T <= 0.
  * Synchronises the stream. */
 lbm_status lbm_init(lbm_ctx* ctx, const double* rho, const double* ux,
                     const double* uy, const double* T);
@@ -155,7 +159,54 @@ lbm_status lbm_step(lbm_ctx* ctx, long long n);
  * with HIP events on the context stream (milliseconds). */
 lbm_status lbm_step_timed(lbm_ctx* ctx, long long n, double* ms);
 
-/* Macroscopic fields at the current time (FP64 host arrays, nx*ny). */
+/* As lbm_step, with options: flags = LBM_STEP_GRAPH captures the n launches
+ * into a HIP graph on first use (one graph per n and start buffer, kept
+ * until the launch configuration changes or the context is destroyed) and
+ * replays it, which removes the per-launch host overhead; ms != NULL
+ * receives the device time of the n steps (HIP events on the context
+ * stream).  Results are bitwise those of lbm_step. */
+#define LBM_STEP_GRAPH 1
+lbm_status lbm_step_ex(lbm_ctx* ctx, long long n, int flags, double* ms);
+
+/* Time level t at the end of the step call that first found case case_id
+ * diverged (the flag is checked once per call, so the divergence happened
+ * within that call's steps), or -1; reset by lbm_init / lbm_load. */
+long long lbm_case_diverged_at(const lbm_ctx* ctx, int case_id);
+
+/* Launch configuration of the step: compiled kernel variant (0: the
+ * hand-tuned one; 1: wave priority by progress flipped; 2: LDS parking of
+ * the row ahead flipped; 3: the other block size, 4 <-> 8 wavefronts),
+ * scale of the modelled cost of an edge-strip row, and row bands per XCD of
+ * the work list.  The physics does not depend on it: results are bitwise
+ * equal for every configuration. */
+lbm_status lbm_set_launch_config(lbm_ctx* ctx, int variant, double xw_scale, int bands_per_xcd);
+
+/* Autotuner of the launch configuration.  If cache_path names a file that
+ * holds an entry for this context's key (device architecture, storage
+ * format, grid and wall signature of its cases), that entry is applied and
+ * no trial runs.  Otherwise every configuration (4 kernel variants x 3
+ * edge-cost scales when a case has x-walls x 2 band counts) is timed over
+ * trial_steps steps (0: about 2e7 node updates) from the current state,
+ * best of three after a warm-up, the state being restored after each trial
+ * (t, buffers, macros and flags are unchanged on return); the fastest is
+ * applied and, if cache_path is not NULL, written to that file (JSON, one
+ * entry per line).  Allocates a device copy of the state while it runs. */
+typedef struct {
+    int variant;
+    double xw_scale;
+    int bands_per_xcd;
+    double ms_per_step;          /* of the chosen configuration */
+    double default_ms_per_step;  /* of configuration (0, 1.0, 4) */
+    int trials;                  /* configurations timed (0: from the cache) */
+    int from_cache;
+} lbm_tune_result;
+lbm_status lbm_autotune(lbm_ctx* ctx, int trial_steps, const char* cache_path, lbm_tune_result* out);
+
+/* Macroscopic fields at the current time (FP64 host arrays, nx*ny, layout
+ * [ny][nx]): rho and u from eq. rho.u (Sec. 2.1, with the half force), T
+ * from eq. E and T = (E - |u|^2/2)/C_v (Sec. 2.2), p = p_EOS(rho, T)
+ * (eqs. EOSs); wall nodes report their prescribed u_b and Dirichlet T_b
+ * (Sec. 3.1).  Written on the last step of each step call.  Synchronises. */
 lbm_status lbm_macros(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* T, double* p);
 
 /* Mean Nusselt number through Dirichlet side `side` (Sec. 4.3):
@@ -167,7 +218,9 @@ lbm_status lbm_macros(lbm_ctx* ctx, double* rho, double* ux, double* uy, double*
 lbm_status lbm_nusselt(lbm_ctx* ctx, int side, double* nu);
 
 /* Sums over all nodes of rho, rho ux, rho uy and rho E (FP64 on the device,
- * fixed reduction order). */
+ * fixed reduction order): the quantities whose local conservation the
+ * collisions (Secs. 2.1, 2.2) and the wall treatment (Sec. 3.2) keep, so a
+ * closed cavity keeps its mass to rounding. */
 lbm_status lbm_totals(lbm_ctx* ctx, double* mass, double* momx, double* momy, double* energy);
 
 /* Checkpoint: a format tag, t, the case count, a record per case (nx, ny,

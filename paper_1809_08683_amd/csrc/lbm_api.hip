@@ -7,28 +7,15 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_launch.hpp"
 #include "lbm_params.hpp"
 
-namespace lbm {
-int launch_step(int prec, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
-                int export_macros, hipStream_t stream);
-int step_blocks_per_cu(int prec);
-int step_lockstep(int prec);
-int step_xwall_in_strips(int prec);
-int step_block_waves(int prec);
-double step_xwall_cost(int prec);
-int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
-                int parity, hipStream_t stream);
-int launch_totals(const CaseParams* d_cases, int case_id, double* d_partial, int nblocks, double* d_out,
-                  hipStream_t stream);
-int launch_nusselt(const CaseParams* d_cases, int case_id, int side, double* d_out, hipStream_t stream);
-int launch_copy(const void* src, void* dst, long long bytes, hipStream_t stream);
-}  // namespace lbm
 
 namespace {
 
@@ -72,6 +59,7 @@ struct CaseHost {
     Layout L;
     char* base = nullptr;     // start of the case's device memory
     bool inited = false;
+    long long diverged_at = -1;   // t at the end of the step call that first saw the case diverged
 };
 
 }  // namespace
@@ -83,6 +71,15 @@ struct lbm_ctx {
     lbm::CaseParams* d_P = nullptr;
     std::vector<lbm::WorkItem> work;     // one entry per wavefront slot of the launch
     lbm::WorkItem* d_work = nullptr;
+    size_t d_work_cap = 0;               // entries d_work can hold
+    int seg_rows = 0;                    // rows per interior item (0: automatic)
+    // launch configuration: kernel variant and work-list settings (lbm_autotune)
+    int variant = 0;
+    double xw_scale = 1.0;
+    int bands_per_xcd = 4;
+    // instantiated graphs of n steps, by (n, start parity); dropped when the
+    // launch configuration changes
+    std::map<std::pair<long long, int>, hipGraphExec_t> graphs;
     long long n_items = 0;               // non-empty entries
     double* d_red = nullptr;
     std::vector<void*> allocs;
@@ -264,7 +261,7 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
 // interior items of a few contiguous bands of rows go to the blocks of one
 // XCD, neighbouring strips of a segment sharing a block.
 bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bool lockstep, bool xw_strips,
-                double xw_cost)
+                double xw_cost, int bands_per_xcd)
 {
     constexpr int NX = 8;
     const int nc = int(c->P.size());
@@ -372,11 +369,11 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
     // cost, each a contiguous run of rows; band j goes to XCD j % 8, whose
     // items fill the free slots of its blocks k, k + 8, ...  (Four bands per
     // XCD measured 0.6-1.7 % faster than one in FP32 and the same in the
-    // other formats.)  With lockstep an XCD's edge items first fill blocks
+    // other formats; the autotuner tries both.)  With lockstep an XCD's edge items first fill blocks
     // of their own, as their rows take longer; without it they are spaced
     // evenly among its other items.  Blocks past the resident count are
     // added if an XCD needs them.  Returns the blocks the launch needs.
-    constexpr int kBands = 4 * NX;
+    const int kBands = std::max(1, bands_per_xcd) * NX;
     auto place = [&](const std::vector<Cand>& items, std::vector<std::pair<long long, lbm::WorkItem>>* out) {
         double total_cost = 0.0;
         for (const auto& it : items) total_cost += it.cost;
@@ -451,6 +448,49 @@ bool build_work(lbm_ctx* c, int seg_rows, int cus, int blocks_per_cu, int PB, bo
     return true;
 }
 
+void drop_graphs(lbm_ctx* c)
+{
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+}
+
+// Sets the launch configuration: step kernel variant, edge-strip cost scale
+// and row bands per XCD; rebuilds and uploads the work list for them.
+lbm_status configure(lbm_ctx* c, int variant, double xw_scale, int bands_per_xcd)
+{
+    if (variant < 0 || variant >= lbm::NUM_STEP_VARIANTS) return fail(c, LBM_EINVAL, "unknown kernel variant");
+    if (!(xw_scale > 0) || bands_per_xcd < 1) return fail(c, LBM_EINVAL, "bad work-list setting");
+    lbm::StepShape sh{};
+    const int e = lbm::step_shape(c->prec, variant, &sh);
+    if (e != 0) return hip_fail(c, hipError_t(e), "step kernel occupancy");
+    int cus = 0;
+    HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    if (!build_work(c, c->seg_rows, cus, sh.blocks_per_cu, sh.block_waves, sh.lockstep != 0, sh.xw_strips != 0,
+                    sh.xw_cost * xw_scale, bands_per_xcd))
+        return fail(c, LBM_EDEVICE, "internal error: inconsistent work list");
+    if (c->work.size() > c->d_work_cap) {
+        if (c->d_work) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            HIP_TRY(c, hipFree(c->d_work));
+            c->d_work = nullptr;
+            c->d_work_cap = 0;
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, sizeof(lbm::WorkItem) * c->work.size()) != hipSuccess)
+            return fail(c, LBM_ENOMEM, "hipMalloc of the work list failed");
+        c->d_work = static_cast<lbm::WorkItem*>(p);
+        c->d_work_cap = c->work.size();
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_work, c->work.data(), sizeof(lbm::WorkItem) * c->work.size(),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->variant = variant;
+    c->xw_scale = xw_scale;
+    c->bands_per_xcd = bands_per_xcd;
+    return LBM_OK;
+}
+
 lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* eos, const double* Pr,
                        const double* gamma, const lbm_relax* relax, const lbm_boundary* bc,
                        const lbm_options* opt, void* dev_ws, size_t ws_bytes, lbm_ctx** out)
@@ -463,8 +503,9 @@ lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* 
     if (!nx || !ny || !eos || !Pr || !gamma || !relax || !bc || !opt)
         return fail(c, LBM_EINVAL, "null parameter block");
     c->prec = opt[0].prec;
+    lbm_status st = LBM_OK;
     for (int k = 0; k < ncases; ++k) {
-        lbm_status st = validate(c, nx[k], ny[k], &eos[k], Pr[k], gamma[k], &relax[k], &bc[k], &opt[k]);
+        st = validate(c, nx[k], ny[k], &eos[k], Pr[k], gamma[k], &relax[k], &bc[k], &opt[k]);
         if (st != LBM_OK) return st;
         if (opt[k].prec != c->prec) return fail(c, LBM_EINVAL, "all cases of a batch share one precision");
     }
@@ -505,25 +546,17 @@ lbm_status create_impl(int ncases, const int* nx, const int* ny, const lbm_eos* 
         c->H[k].base = base + off;
         off += L[k].total;
     }
-    int cus = 0;
-    HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-    if (!build_work(c, opt[0].seg_rows, cus, lbm::step_blocks_per_cu(c->prec),
-                    lbm::step_block_waves(c->prec), lbm::step_lockstep(c->prec) != 0,
-                    lbm::step_xwall_in_strips(c->prec) != 0, lbm::step_xwall_cost(c->prec)))
-        return fail(c, LBM_EDEVICE, "internal error: inconsistent work list");
     void* p = nullptr;
     HIP_TRY(c, hipMalloc(&p, sizeof(lbm::CaseParams) * ncases));
     c->allocs.push_back(p);
     c->d_P = static_cast<lbm::CaseParams*>(p);
-    HIP_TRY(c, hipMalloc(&p, sizeof(lbm::WorkItem) * c->work.size()));
-    c->allocs.push_back(p);
-    c->d_work = static_cast<lbm::WorkItem*>(p);
+    c->seg_rows = opt[0].seg_rows;
+    st = configure(c, 0, 1.0, 4);
+    if (st != LBM_OK) return st;
     HIP_TRY(c, hipMalloc(&p, sizeof(double) * (kRedBlocks * 4 + 8)));
     c->allocs.push_back(p);
     c->d_red = static_cast<double*>(p);
     HIP_TRY(c, hipMemcpyAsync(c->d_P, c->P.data(), sizeof(lbm::CaseParams) * ncases, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->d_work, c->work.data(), sizeof(lbm::WorkItem) * c->work.size(),
-                              hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
@@ -571,26 +604,184 @@ CkptCase ckpt_case(const lbm_ctx* c, size_t k)
     return CkptCase{h.nx, h.ny, c->prec, h.L.pitch, (long long)h.L.buf_bytes, (long long)h.L.macro_bytes};
 }
 
-lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t e0, hipEvent_t e1)
+// Enqueues n step launches starting from buffer `parity` (no host waits).
+int enqueue_steps(lbm_ctx* c, long long n, int parity)
+{
+    for (long long s = 0; s < n; ++s) {
+        const int rc = lbm::launch_step(c->prec, c->variant, c->d_P, c->d_work, int(c->work.size()), parity,
+                                        s == n - 1 ? 1 : 0, c->stream);
+        if (rc != 0) return rc;
+        parity ^= 1;
+    }
+    return 0;
+}
+
+// The graph of n steps from start parity p: captured from the launch
+// sequence on first use, then reused (the kernel arguments depend only on
+// n, p and the launch configuration).
+lbm_status step_graph(lbm_ctx* c, long long n, hipGraphExec_t* out)
+{
+    const auto key = std::make_pair(n, c->parity);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) {
+        *out = it->second;
+        return LBM_OK;
+    }
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_steps(c, n, c->parity);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc != 0 || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(c, rc != 0 ? hipError_t(rc) : e, "step graph capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return hip_fail(c, ei, "step graph instantiate");
+    c->graphs[key] = exec;
+    *out = exec;
+    return LBM_OK;
+}
+
+lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t e0, hipEvent_t e1, bool graph = false)
 {
     for (size_t k = 0; k < c->H.size(); ++k)
         if (!c->H[k].inited) return fail(c, LBM_ESTATE, "lbm_step before lbm_init of every case");
     if (n < 0) return fail(c, LBM_EINVAL, "negative step count");
-    if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
-    for (long long s = 0; s < n; ++s) {
-        const int rc = lbm::launch_step(c->prec, c->d_P, c->d_work, int(c->work.size()), c->parity,
-                                        s == n - 1 ? 1 : 0, c->stream);
-        if (rc != 0) return hip_fail(c, hipError_t(rc), "step launch");
-        c->parity ^= 1;
+    hipGraphExec_t exec = nullptr;
+    if (graph && n > 0) {
+        lbm_status st = step_graph(c, n, &exec);
+        if (st != LBM_OK) return st;
     }
+    if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
+    if (exec) {
+        HIP_TRY(c, hipGraphLaunch(exec, c->stream));
+    } else {
+        const int rc = enqueue_steps(c, n, c->parity);
+        if (rc != 0) return hip_fail(c, hipError_t(rc), "step launch");
+    }
+    c->parity ^= int(n & 1);
     if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
+    const long long t0 = c->t;
     c->t += n;
     std::vector<int> flags;
     lbm_status st = read_flags(c, flags);
     if (st != LBM_OK) return st;
     for (size_t k = 0; k < flags.size(); ++k)
-        if (flags[k]) return fail(c, LBM_EDIVERGED, "case " + std::to_string(k) + " diverged");
+        if (flags[k]) {
+            if (c->H[k].diverged_at < 0) c->H[k].diverged_at = c->t;
+            return fail(c, LBM_EDIVERGED, "case " + std::to_string(k) + " diverged (first seen after the step call " +
+                                              "that ended at t = " + std::to_string(c->H[k].diverged_at) +
+                                              "; this call covered t = " + std::to_string(t0) + " .. " +
+                                              std::to_string(c->t) + ")");
+        }
     return LBM_OK;
+}
+
+// ---- autotuner -------------------------------------------------------------
+struct TuneEntry {
+    int variant = 0;
+    double xw_scale = 1.0;
+    int bands = 4;
+    double ms = 0.0, ms_default = 0.0;
+};
+
+unsigned long long fnv1a(unsigned long long h, long long v)
+{
+    for (int b = 0; b < 8; ++b) {
+        h ^= (unsigned long long)((v >> (8 * b)) & 0xff);
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+// Cache key: device architecture, storage format and the shape signature of
+// the cases (grid, walls), which is all the launch configuration depends on.
+std::string tune_key(const lbm_ctx* c)
+{
+    static const char* prec_name[4] = {"f64", "f32", "f16s", "f32g16"};
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+    }
+    std::string key = arch + "|" + prec_name[c->prec & 3] + "|n" + std::to_string(c->P.size()) + "|";
+    if (c->P.size() == 1) {
+        const auto& P = c->P[0];
+        key += std::to_string(P.nx) + "x" + std::to_string(P.ny) + "|w" + std::to_string(P.wall_x) +
+               std::to_string(P.wall_y);
+    } else {
+        unsigned long long h = 1469598103934665603ULL;
+        long long nodes = 0;
+        for (const auto& P : c->P) {
+            h = fnv1a(h, P.nx);
+            h = fnv1a(h, P.ny);
+            h = fnv1a(h, P.wall_x * 2 + P.wall_y);
+            nodes += (long long)P.nx * P.ny;
+        }
+        char hex[24];
+        std::snprintf(hex, sizeof hex, "%016llx", h);
+        key += "nodes" + std::to_string(nodes) + "|h" + hex;
+    }
+    if (c->seg_rows > 0) key += "|seg" + std::to_string(c->seg_rows);
+    return key;
+}
+
+double json_number(const std::string& line, const char* name, double dflt)
+{
+    const std::string pat = std::string("\"") + name + "\":";
+    const size_t at = line.find(pat);
+    if (at == std::string::npos) return dflt;
+    return std::strtod(line.c_str() + at + pat.size(), nullptr);
+}
+
+// The cache file is the JSON object this library writes: one entry per line,
+// "key": {"variant": v, "xw_scale": x, "bands_per_xcd": b, "ms_per_step": t,
+// "default_ms_per_step": t0}.
+std::map<std::string, TuneEntry> read_tune_cache(const char* path)
+{
+    std::map<std::string, TuneEntry> m;
+    FILE* f = path ? std::fopen(path, "r") : nullptr;
+    if (!f) return m;
+    char buf[1024];
+    while (std::fgets(buf, sizeof buf, f)) {
+        const std::string line(buf);
+        const size_t q0 = line.find('"');
+        if (q0 == std::string::npos || line.find("\"variant\":") == std::string::npos) continue;
+        const size_t q1 = line.find('"', q0 + 1);
+        if (q1 == std::string::npos) continue;
+        TuneEntry e;
+        e.variant = int(json_number(line, "variant", 0));
+        e.xw_scale = json_number(line, "xw_scale", 1.0);
+        e.bands = int(json_number(line, "bands_per_xcd", 4));
+        e.ms = json_number(line, "ms_per_step", 0.0);
+        e.ms_default = json_number(line, "default_ms_per_step", 0.0);
+        m[line.substr(q0 + 1, q1 - q0 - 1)] = e;
+    }
+    std::fclose(f);
+    return m;
+}
+
+bool write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& m)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto& kv : m) {
+        const TuneEntry& e = kv.second;
+        std::fprintf(f,
+                     "  \"%s\": {\"variant\": %d, \"xw_scale\": %.3f, \"bands_per_xcd\": %d, "
+                     "\"ms_per_step\": %.6f, \"default_ms_per_step\": %.6f}%s\n",
+                     kv.first.c_str(), e.variant, e.xw_scale, e.bands, e.ms, e.ms_default, ++i < m.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
 }
 
 }  // namespace
@@ -710,6 +901,7 @@ lbm_status lbm_case_init(lbm_ctx* c, int k, const double* rho, const double* ux,
     if (e != hipSuccess) return hip_fail(c, e, "lbm_init");
     if (rc != 0) return hip_fail(c, hipError_t(rc), "init launch");
     c->H[k].inited = true;
+    c->H[k].diverged_at = -1;
     if (c->P.size() == 1) c->t = 0;
     return LBM_OK;
 }
@@ -781,6 +973,150 @@ lbm_status lbm_step_timed(lbm_ctx* c, long long n, double* ms)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return st;
+}
+
+lbm_status lbm_step_ex(lbm_ctx* c, long long n, int flags, double* ms)
+{
+    lbm_status st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (flags & ~LBM_STEP_GRAPH) return fail(c, LBM_EINVAL, "unknown step flags");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ms) {
+        HIP_TRY(c, hipEventCreate(&e0));
+        HIP_TRY(c, hipEventCreate(&e1));
+    }
+    st = run_steps(c, n, e0, e1, (flags & LBM_STEP_GRAPH) != 0);
+    if (ms && (st == LBM_OK || st == LBM_EDIVERGED)) {
+        float f = 0.f;
+        if (hipEventElapsedTime(&f, e0, e1) == hipSuccess) *ms = f;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return st;
+}
+
+long long lbm_case_diverged_at(const lbm_ctx* c, int k)
+{
+    if (!c || k < 0 || k >= int(c->H.size())) return -1;
+    return c->H[k].diverged_at;
+}
+
+lbm_status lbm_set_launch_config(lbm_ctx* c, int variant, double xw_scale, int bands_per_xcd)
+{
+    lbm_status st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    return configure(c, variant, xw_scale, bands_per_xcd);
+}
+
+lbm_status lbm_autotune(lbm_ctx* c, int trial_steps, const char* cache_path, lbm_tune_result* out)
+{
+    lbm_status st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    for (const auto& h : c->H)
+        if (!h.inited) return fail(c, LBM_ESTATE, "lbm_autotune before lbm_init of every case");
+    if (trial_steps < 0) return fail(c, LBM_EINVAL, "negative trial step count");
+    const std::string key = tune_key(c);
+    std::map<std::string, TuneEntry> cache = read_tune_cache(cache_path);
+    auto hit = cache.find(key);
+    if (hit != cache.end()) {
+        const TuneEntry& e = hit->second;
+        st = configure(c, e.variant, e.xw_scale, e.bands);
+        if (st != LBM_OK) return st;
+        if (out) *out = lbm_tune_result{e.variant, e.xw_scale, e.bands, e.ms, e.ms_default, 0, 1};
+        return LBM_OK;
+    }
+    long long nodes = 0;
+    bool xwall = false;
+    for (const auto& P : c->P) {
+        nodes += (long long)P.nx * P.ny;
+        xwall = xwall || P.wall_x;
+    }
+    if (trial_steps == 0) trial_steps = int(std::min<long long>(200, std::max<long long>(5, 20000000LL / std::max(nodes, 1LL))));
+    // the trials advance the state: keep the current buffer, macros and flag
+    // of every case and put them back after each trial
+    size_t bytes = 0;
+    for (const auto& h : c->H) bytes += h.L.buf_bytes + h.L.macro_bytes + h.L.flag_bytes;
+    void* backup = nullptr;
+    if (hipMalloc(&backup, bytes) != hipSuccess) return fail(c, LBM_ENOMEM, "hipMalloc of the tuner's state copy failed");
+    const int parity0 = c->parity;
+    const long long t0 = c->t;
+    auto copy_state = [&](bool save) -> hipError_t {
+        char* b = static_cast<char*>(backup);
+        for (const auto& h : c->H) {
+            char* cur = h.base + parity0 * h.L.buf_bytes;
+            char* rest = h.base + 2 * h.L.buf_bytes;   // macros, then the flag
+            const size_t rb = h.L.macro_bytes + h.L.flag_bytes;
+            hipError_t e = hipMemcpyAsync(save ? b : cur, save ? cur : b, h.L.buf_bytes, hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) return e;
+            b += h.L.buf_bytes;
+            e = hipMemcpyAsync(save ? b : rest, save ? rest : b, rb, hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) return e;
+            b += rb;
+        }
+        return hipStreamSynchronize(c->stream);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = copy_state(true);
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    const int v0 = c->variant;
+    const double x0 = c->xw_scale;
+    const int b0 = c->bands_per_xcd;
+    TuneEntry best, dflt;
+    best.ms = 1e300;
+    int trials = 0;
+    const double scales[3] = {1.0, 0.85, 1.2};
+    const int bands[2] = {4, 1};
+    for (int v = 0; v < lbm::NUM_STEP_VARIANTS && he == hipSuccess && st == LBM_OK; ++v)
+        for (int si = 0; si < (xwall ? 3 : 1) && he == hipSuccess && st == LBM_OK; ++si)
+            for (int bi = 0; bi < 2 && he == hipSuccess && st == LBM_OK; ++bi) {
+                st = configure(c, v, scales[si], bands[bi]);
+                if (st != LBM_OK) break;
+                double ms_best = 1e300;
+                for (int rep = 0; rep < 4; ++rep) {   // the first run warms up
+                    he = copy_state(false);
+                    if (he != hipSuccess) break;
+                    c->parity = parity0;
+                    const lbm_status rs = run_steps(c, trial_steps, e0, e1);
+                    if (rs != LBM_OK && rs != LBM_EDIVERGED) {
+                        st = rs;
+                        break;
+                    }
+                    float f = 0.f;
+                    he = hipEventElapsedTime(&f, e0, e1);
+                    if (he != hipSuccess) break;
+                    if (rep > 0) ms_best = std::min(ms_best, double(f) / trial_steps);
+                }
+                ++trials;
+                if (v == 0 && si == 0 && bi == 0) dflt.ms = ms_best;
+                if (ms_best < best.ms) {
+                    best.variant = v;
+                    best.xw_scale = scales[si];
+                    best.bands = bands[bi];
+                    best.ms = ms_best;
+                }
+            }
+    if (he == hipSuccess) he = copy_state(false);
+    c->parity = parity0;
+    c->t = t0;
+    for (auto& h : c->H) h.diverged_at = -1;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(backup);
+    if (st == LBM_OK && he != hipSuccess) st = hip_fail(c, he, "autotune trial");
+    if (st != LBM_OK) {
+        (void)configure(c, v0, x0, b0);
+        return st;
+    }
+    best.ms_default = dflt.ms;
+    st = configure(c, best.variant, best.xw_scale, best.bands);
+    if (st != LBM_OK) return st;
+    if (cache_path) {
+        cache[key] = best;
+        if (!write_tune_cache(cache_path, cache)) return fail(c, LBM_EINVAL, "cannot write the tuning cache file");
+    }
+    if (out) *out = lbm_tune_result{best.variant, best.xw_scale, best.bands, best.ms, best.ms_default, trials, 0};
+    return LBM_OK;
 }
 
 lbm_status lbm_case_macros(lbm_ctx* c, int k, double* rho, double* ux, double* uy, double* T, double* p)
@@ -920,6 +1256,7 @@ lbm_status lbm_load(lbm_ctx* c, const void* host, size_t bytes)
         o += h.L.macro_bytes;
         HIP_TRY(c, hipMemsetAsync(c->P[k].flag, 0, sizeof(int), c->stream));
         h.inited = true;
+        h.diverged_at = -1;
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->t = hdr[0];
@@ -969,6 +1306,8 @@ void lbm_destroy(lbm_ctx* c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->d_work) (void)hipFree(c->d_work);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;

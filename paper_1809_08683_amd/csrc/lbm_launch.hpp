@@ -1,0 +1,44 @@
+// Host-side entry points of the step, initialisation and reduction kernels
+// (lbm_kernels.hip and the per-format lbm_step_<format>.hip units).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lbm_params.hpp"
+
+namespace lbm {
+
+// Tuning variants compiled per storage format (see lbm_step.hpp).
+constexpr int NUM_STEP_VARIANTS = 4;
+
+// What the work list of a step kernel variant must follow.
+struct StepShape {
+    int lockstep;        // interior waves of a block march row by row together
+    int xw_strips;       // strips next to an x-wall collide its nodes
+    int block_waves;     // wavefronts per block
+    int blocks_per_cu;   // resident blocks per CU
+    double xw_cost;      // time of an edge-strip row relative to a plain row
+};
+
+int launch_step(int prec, int variant, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
+                int export_macros, hipStream_t stream);
+int step_shape(int prec, int variant, StepShape* out);
+int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
+                int parity, hipStream_t stream);
+int launch_totals(const CaseParams* d_cases, int case_id, double* d_partial, int nblocks, double* d_out,
+                  hipStream_t stream);
+int launch_nusselt(const CaseParams* d_cases, int case_id, int side, double* d_out, hipStream_t stream);
+int launch_copy(const void* src, void* dst, long long bytes, hipStream_t stream);
+
+#define LBM_DECLARE_FORMAT(NAME)                                                                             \
+    int launch_step_##NAME(int variant, const CaseParams* d_cases, const WorkItem* d_work, int nwork,        \
+                           int parity, int export_macros, hipStream_t stream);                               \
+    int step_shape_##NAME(int variant, StepShape* out);                                                      \
+    int launch_init_##NAME(const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,  \
+                           int parity, hipStream_t stream);
+LBM_DECLARE_FORMAT(f64)
+LBM_DECLARE_FORMAT(f32)
+LBM_DECLARE_FORMAT(f16)
+LBM_DECLARE_FORMAT(f32g16)
+#undef LBM_DECLARE_FORMAT
+
+}  // namespace lbm

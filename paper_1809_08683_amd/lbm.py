@@ -60,6 +60,15 @@ class Options(C.Structure):
                 ("hip_stream", C.c_void_p)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("variant", C.c_int), ("xw_scale", C.c_double), ("bands_per_xcd", C.c_int),
+                ("ms_per_step", C.c_double), ("default_ms_per_step", C.c_double), ("trials", C.c_int),
+                ("from_cache", C.c_int)]
+
+
+STEP_GRAPH = 1
+TUNE_CACHE = os.path.join(_HERE, "tune_cache.json")
+
 _lib = None
 _D = C.POINTER(C.c_double)
 
@@ -89,6 +98,10 @@ def load_library():
         "lbm_init": ([vp, _D, _D, _D, _D], C.c_int),
         "lbm_step": ([vp, C.c_longlong], C.c_int),
         "lbm_step_timed": ([vp, C.c_longlong, _D], C.c_int),
+        "lbm_step_ex": ([vp, C.c_longlong, C.c_int, _D], C.c_int),
+        "lbm_case_diverged_at": ([vp, C.c_int], C.c_longlong),
+        "lbm_set_launch_config": ([vp, C.c_int, C.c_double, C.c_int], C.c_int),
+        "lbm_autotune": ([vp, C.c_int, C.c_char_p, C.POINTER(TuneResult)], C.c_int),
         "lbm_macros": ([vp, _D, _D, _D, _D, _D], C.c_int),
         "lbm_nusselt": ([vp, C.c_int, _D], C.c_int),
         "lbm_totals": ([vp, _D, _D, _D, _D], C.c_int),
@@ -121,7 +134,7 @@ def load_library():
 def exported_symbols():
     """Names of the C ABI entry points this binding calls."""
     return ["lbm_create", "lbm_workspace_bytes", "lbm_create_ex", "lbm_init", "lbm_step",
-            "lbm_step_timed", "lbm_macros", "lbm_nusselt", "lbm_totals", "lbm_state_bytes",
+            "lbm_step_timed", "lbm_step_ex", "lbm_case_diverged_at", "lbm_set_launch_config", "lbm_autotune", "lbm_macros", "lbm_nusselt", "lbm_totals", "lbm_state_bytes",
             "lbm_save", "lbm_load", "lbm_time", "lbm_last_error", "lbm_destroy",
             "lbm_batch_create", "lbm_batch_size", "lbm_case_init", "lbm_case_init_static", "lbm_case_macros",
             "lbm_case_nusselt", "lbm_case_totals", "lbm_batch_flags", "lbm_work_items",
@@ -210,6 +223,32 @@ class _Base:
         if not (rc == EDIVERGED and allow_diverged):
             self._check(rc, "lbm_step_timed")
         return ms.value
+
+    def step_ex(self, n: int, graph: bool = False, allow_diverged: bool = False) -> float:
+        """Advance n steps (as one replayed HIP graph if ``graph``); return
+        their device time (ms)."""
+        ms = C.c_double(0.0)
+        rc = self.lib.lbm_step_ex(self.h, int(n), STEP_GRAPH if graph else 0, C.byref(ms))
+        self.diverged = rc == EDIVERGED
+        if not (rc == EDIVERGED and allow_diverged):
+            self._check(rc, "lbm_step_ex")
+        return ms.value
+
+    def diverged_at(self, k: int = 0) -> int:
+        return int(self.lib.lbm_case_diverged_at(self.h, int(k)))
+
+    def set_launch_config(self, variant: int = 0, xw_scale: float = 1.0, bands_per_xcd: int = 4):
+        self._check(self.lib.lbm_set_launch_config(self.h, int(variant), float(xw_scale), int(bands_per_xcd)),
+                    "lbm_set_launch_config")
+        return self
+
+    def autotune(self, trial_steps: int = 0, cache_path=TUNE_CACHE) -> dict:
+        """Launch-configuration autotuner (see lbm_autotune); cache_path None
+        tunes without reading or writing a cache."""
+        r = TuneResult()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self.lib.lbm_autotune(self.h, int(trial_steps), path, C.byref(r)), "lbm_autotune")
+        return {n: getattr(r, n) for n, _ in TuneResult._fields_}
 
     @property
     def time(self) -> int:
