@@ -185,12 +185,15 @@ lbm_status lbm_set_launch_config(lbm_ctx* ctx, int variant, double xw_scale, int
  * holds an entry for this context's key (device architecture, storage
  * format, grid and wall signature of its cases), that entry is applied and
  * no trial runs.  Otherwise every configuration (4 kernel variants x 3
- * edge-cost scales when a case has x-walls x 2 band counts) is timed over
+ * edge-cost scales when a case has x-walls x 3 band counts: 4, 1, 16 per
+ * XCD) is timed over
  * trial_steps steps (0: about 2e7 node updates) from the current state,
  * best of three after a warm-up, the state being restored after each trial
  * (t, buffers, macros and flags are unchanged on return); the fastest is
- * applied and, if cache_path is not NULL, written to that file (JSON, one
- * entry per line).  Allocates a device copy of the state while it runs. */
+ * applied if it beats the default configuration (0, 1.0, 4) by more than
+ * 1 %, else the default is kept; the choice is written to cache_path if it
+ * is not NULL (JSON, one entry per line).  Allocates a device copy of the
+ * state while it runs. */
 typedef struct {
     int variant;
     double xw_scale;
@@ -262,6 +265,17 @@ lbm_status lbm_case_totals(lbm_ctx* ctx, int case_id, double* mass, double* momx
  * context stream before returning. */
 lbm_status lbm_case_init_static(lbm_ctx* ctx, int case_id, const double* rho, const double* ux,
                                 const double* uy, const double* T);
+
+/* The batch calls in the survey's form: lbm_batch_step advances every case
+ * n steps and, unlike lbm_step, returns LBM_OK when cases diverged (their
+ * flags are reported per case); lbm_batch_nusselt writes, for every case,
+ * its divergence flag (1: diverged) and its mean Nusselt number through
+ * Dirichlet side `side` as lbm_case_nusselt computes it (NaN for a case
+ * that diverged, is not initialised, or has no Dirichlet pair with a
+ * temperature difference on that axis).  nu and diverged are caller-owned
+ * arrays of lbm_batch_size(ctx) entries.  LBM_EINVAL for side outside 0-3. */
+lbm_status lbm_batch_step(lbm_ctx* ctx, long long n);
+lbm_status lbm_batch_nusselt(lbm_ctx* ctx, int side, double* nu, int* diverged);
 
 /* Divergence flag of each case (1: diverged) after the last step call. */
 lbm_status lbm_batch_flags(lbm_ctx* ctx, int* diverged);

@@ -120,6 +120,8 @@ def load_library():
         "lbm_case_nusselt": ([vp, C.c_int, C.c_int, _D], C.c_int),
         "lbm_case_totals": ([vp, C.c_int, _D, _D, _D, _D], C.c_int),
         "lbm_batch_flags": ([vp, C.POINTER(C.c_int)], C.c_int),
+        "lbm_batch_step": ([vp, C.c_longlong], C.c_int),
+        "lbm_batch_nusselt": ([vp, C.c_int, _D, C.POINTER(C.c_int)], C.c_int),
         "lbm_work_items": ([vp], C.c_longlong),
         "lbm_copy_bandwidth": ([C.c_size_t, C.c_int, vp, _D, _D], C.c_int),
     }
@@ -137,7 +139,7 @@ def exported_symbols():
             "lbm_step_timed", "lbm_step_ex", "lbm_case_diverged_at", "lbm_set_launch_config", "lbm_autotune", "lbm_macros", "lbm_nusselt", "lbm_totals", "lbm_state_bytes",
             "lbm_save", "lbm_load", "lbm_time", "lbm_last_error", "lbm_destroy",
             "lbm_batch_create", "lbm_batch_size", "lbm_case_init", "lbm_case_init_static", "lbm_case_macros",
-            "lbm_case_nusselt", "lbm_case_totals", "lbm_batch_flags", "lbm_work_items",
+            "lbm_case_nusselt", "lbm_case_totals", "lbm_batch_flags", "lbm_batch_step", "lbm_batch_nusselt", "lbm_work_items",
             "lbm_copy_bandwidth"]
 
 
@@ -382,6 +384,19 @@ class Batch(_Base):
         v = [C.c_double() for _ in range(4)]
         self._check(self.lib.lbm_case_totals(self.h, int(k), *[C.byref(x) for x in v]), "lbm_case_totals")
         return tuple(x.value for x in v)
+
+    def batch_step(self, n: int):
+        """Advance every case n steps; divergence is reported per case."""
+        self._check(self.lib.lbm_batch_step(self.h, int(n)), "lbm_batch_step")
+        return self
+
+    def batch_nusselt(self, side: int = 0):
+        """(nu, diverged) of every case."""
+        n = len(self.cases)
+        nu = np.empty(n)
+        dv = (C.c_int * n)()
+        self._check(self.lib.lbm_batch_nusselt(self.h, int(side), _ptr(nu), dv), "lbm_batch_nusselt")
+        return nu, list(dv)
 
     def flags(self):
         out = (C.c_int * len(self.cases))()

@@ -153,3 +153,29 @@ def test_batch_sweep_configuration():
         o.step(10)
         check(b.macros(k), o.macros(), "f32", f"sweep case {k} N={c['nx']} Ra={c['Ra']:.3g}")
     b.close()
+
+
+def test_batch_step_and_nusselt_in_survey_form():
+    """lbm_batch_step / lbm_batch_nusselt: every case's flag and Nu through
+    the x = 0 wall, NaN for the diverged channel (the paper's unstable set of
+    Sec. 4.1, Pr = 0.1, which has no x-walls anyway), the cavities' equal to
+    lbm_case_nusselt."""
+    U0 = 0.2 * np.sqrt(1 / 3)
+    bad = inputs.base_case(nx=3, ny=33, eos="ideal", nu0=0.1, Pr=0.1, force=(8 * 0.1 * U0 / 32 ** 2, 0.0),
+                           sides=[P(), P(), W(T=1.0), W(T=1.0 + U0 ** 2 / ((3.5 / 3) * 10))], extrap_order=2)
+    good = [_cavity(13, ny=11), _cavity(40, ny=24, eps=0.2)]
+    cases = [good[0], bad, good[1]]
+    b = lbm.Batch(cases)
+    for k in range(3):
+        b.init(k)
+    for _ in range(50):
+        b.batch_step(100)
+        if b.flags()[1]:
+            break
+    b.batch_step(10)
+    nu, dv = b.batch_nusselt(0)
+    assert dv == [0, 1, 0]
+    assert np.isnan(nu[1])
+    for k in (0, 2):
+        assert nu[k] == b.nusselt(k, 0)
+    b.close()

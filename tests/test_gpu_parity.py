@@ -333,24 +333,40 @@ def _nu_run(prec, steps):
     return nu
 
 
+_NU256 = {}
+
+
+def _nu256(prec):
+    if prec not in _NU256:
+        _NU256[prec] = _nu_run(prec, 100000)
+    return _NU256[prec]
+
+
 def test_nusselt_cavity_256_against_table2_and_fp64(golden):
     """256^2 cavity, Ra = 1e5, eps = 0.6 (Table 1 pairing), 100000 steps:
     the FP64 path reaches a steady mean hot-wall Nu within 1% of the value
     Table 2 prints for this Rayleigh number (4.4836), and the FP32 path and
     the FP32-f / FP16-g path stay within 0.5% of the FP64 path (whose every
-    step matches the oracle to 1e-10 in the parity tests above).  The
-    FP16-offset path is reported: its 16-bit density DFs limit it to about
-    10% here."""
+    step matches the oracle to 1e-10 in the parity tests above)."""
     t2 = golden["cavity_table2_present"]
     ref = t2["Nu_ave"][t2["Ra"].index(1e5)]
-    nu = {p: _nu_run(p, 100000) for p in ("f64", "f32", "f32g16", "f16s")}
+    nu = {p: _nu256(p) for p in ("f64", "f32", "f32g16")}
     rel = {p: (nu[p] - nu["f64"]) / nu["f64"] for p in nu}
     print("Nu", {p: round(v, 5) for p, v in nu.items()}, "rel vs f64", {p: f"{v:.1e}" for p, v in rel.items()},
           f"f64 vs Table 2: {(nu['f64'] - ref) / ref:.2e}", flush=True)
     assert abs(nu["f64"] - ref) / ref < 0.01
     assert abs(rel["f32"]) < 5e-3
     assert abs(rel["f32g16"]) < 5e-3
-    assert np.isfinite(nu["f16s"]) and abs(rel["f16s"]) < 0.25
+
+
+@pytest.mark.xfail(strict=True, reason="FP16 storage of the density DFs: Nu about 12 % from FP64 here "
+                                       "(a spatially varying reference state does not help; see the design notes)")
+def test_fp16s_nusselt_within_half_percent_of_fp64():
+    """The same cavity in the FP16-offset format held to the 0.5 % bar."""
+    nu16, nu64 = _nu256("f16s"), _nu256("f64")
+    rel = (nu16 - nu64) / nu64
+    print(f"FP16S Nu {nu16:.5f} vs FP64 {nu64:.5f}: {rel:.2e}", flush=True)
+    assert np.isfinite(nu16) and abs(rel) < 5e-3
 
 
 def test_fp32_nusselt_tracks_fp64_on_a_fine_grid():
