@@ -101,14 +101,14 @@ typedef struct {
  *   FP32   - FP32 storage and arithmetic, temperature recovered in FP64;
  *   FP16S  - FP16 storage of f and g, FP32 arithmetic, temperature in FP64;
  *   F32G16 - FP32 storage of the density DFs f, FP16 storage of the
- *            energy DFs g, FP32 arithmetic, temperature in FP64 (the 16-bit
- *            density DFs are what limits FP16S accuracy).
- * The 16-bit formats lose accuracy as the grid is refined at fixed
- * viscosity: the change of a DF per step shrinks with the grid while the
- * rounding of its stored offset does not.  On a cavity with eps = 0.6 their
- * mean Nusselt number is within 0.3 % (F32G16) and 12 % (FP16S) of FP64 at
- * 256^2, but off by percents (F32G16) or several times (FP16S) from 512^2
- * on, and F32G16 can become unstable there; FP32 stays within 5e-4. */
+ *            energy DFs g, FP32 arithmetic, temperature in FP64.
+ * The 16-bit rows are rounded stochastically (unbiased; the random byte of a
+ * value depends only on its node, row and step, so results are bitwise
+ * reproducible), and with an ideal gas between two Dirichlet x-walls the g
+ * rows store offsets from the conduction state between them instead of the
+ * global rest state.  On a cavity with eps = 0.6 the mean Nusselt number
+ * then stays within 0.11 % (F32G16) and 0.45 % (FP16S; 0.9 % early in a
+ * 1024^2 transient) of FP64 up to 2048^2; FP32 within 5e-4. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2, LBM_F32G16 = 3 } lbm_precision;
 
 typedef struct {
@@ -289,6 +289,17 @@ long long  lbm_work_items(const lbm_ctx* ctx);
  * Used as the measured-bandwidth reference of the roofline and to calibrate
  * hardware byte counters. */
 lbm_status lbm_copy_bandwidth(size_t bytes, int iters, void* hip_stream, double* gbps, double* ms_per_copy);
+
+/* Stochastic rounding of the 16-bit formats, computed on the host with the
+ * kernels' own code (no GPU needed; for tests and diagnostics).
+ * lbm_rounding_byte: the random byte (0-255) with which DF row q (0-8 f,
+ * 9-17 g) of node (x, y) is rounded when stored in step t under storage
+ * precision prec; 0 for rows that the precision does not store in 16 bits,
+ * for prec outside lbm_precision and for q outside 0-17.
+ * lbm_round_half_stochastic: the FP16 value, returned as float, that v is
+ * stored as with random byte u (u mod 256). */
+unsigned   lbm_rounding_byte(int prec, int x, int y, unsigned t, int q);
+float      lbm_round_half_stochastic(float v, unsigned u);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 // Host runtime and C ABI (include/lbm.h) of the gfx950 lattice Boltzmann
 // library: parameter validation and derived constants, device memory, the
 // per-step work list, launches, reductions and checkpoints.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,6 +16,7 @@
 #include "lbm.h"
 #include "lbm_launch.hpp"
 #include "lbm_params.hpp"
+#include "lbm_rounding.hpp"
 
 
 namespace {
@@ -24,6 +26,9 @@ constexpr double kCs2 = 1.0 / 3.0;
 constexpr double kVarpi = 1.0 / 6.0, kGamma1 = -2.0, kGamma2 = 2.0;
 constexpr double kKappa = 2.0 / 3.0 + kGamma1 / 2.0 + kGamma2 / 3.0;
 constexpr int kRedBlocks = 240;
+// Per-case flag area (256 bytes after the macro arrays): the divergence flag
+// at byte 0, the two step counters of the stochastic rounding at byte 64.
+constexpr size_t kTickOffset = 64;
 
 // bytes of one f value and of one g value as stored
 size_t f_size(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP16S ? 2 : 4); }
@@ -215,6 +220,12 @@ lbm_status validate(lbm_ctx* c, int nx, int ny, const lbm_eos* eos, double Pr, d
     return LBM_OK;
 }
 
+// whether a case's 16-bit g rows are stored relative to the conduction state
+bool gref_applies(const lbm_eos& e, const lbm_boundary& bc)
+{
+    return e.kind == LBM_EOS_IDEAL && bc.side[0].wall && !bc.side[0].adiabatic && !bc.side[1].adiabatic;
+}
+
 void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr, double gamma,
                 const lbm_relax& r, const lbm_boundary& bc, const lbm_options& o, const Layout& L,
                 char* base)
@@ -240,12 +251,25 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
     P.buf[1] = base + L.buf_bytes;
     P.macro = reinterpret_cast<double*>(base + 2 * L.buf_bytes);
     P.flag = reinterpret_cast<int*>(base + 2 * L.buf_bytes + L.macro_bytes);
+    P.tick = reinterpret_cast<unsigned*>(base + 2 * L.buf_bytes + L.macro_bytes + kTickOffset);
 
     const double R = gas_constant(e);
     const double cp = o.cp > 0 ? o.cp : 3.5 * kCs2 / e.T0;
     const double cv = o.cv_rule ? cp - pressure(e, R, e.rho0, e.T0) / (e.rho0 * e.T0) : cp / gamma;
     fill_coef<double>(P.cd, e, R, cp, cv, Pr, r, o, bc);
     fill_coef<float>(P.cf, e, R, cp, cv, Pr, r, o, bc);
+    // 16-bit g rows store offsets from the rest equilibrium of the conduction
+    // state between two Dirichlet x-walls (ideal gas: T_ref linear from side 0
+    // at x = 0 to side 1 at x = nx - 1, rho_ref T_ref = rho0 T0),
+    // s(x) = rho0 C_p (T_ref(x) - T0)
+    if ((o.prec == LBM_F32G16 || o.prec == LBM_FP16S) && gref_applies(e, bc)) {
+        const double s0 = e.rho0 * cp * (bc.side[0].T - e.T0);
+        const double k = e.rho0 * cp * (bc.side[1].T - bc.side[0].T) / double(nx - 1);
+        P.cd.gs0 = s0;
+        P.cd.gsk = k;
+        P.cf.gs0 = float(s0);
+        P.cf.gsk = float(k);
+    }
 }
 
 // Work decomposition of one step.  The off-wall region of every case is cut
@@ -588,21 +612,28 @@ lbm_status read_flags(lbm_ctx* c, std::vector<int>& flags)
 // Checkpoint layout: an 8-byte format tag, t and the case count, one
 // CkptCase record per case, then per case the current DF buffer and the
 // macro array.  lbm_load accepts a checkpoint only if every record equals the
-// context's own.
-constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '2'};
+// context's own.  The record includes the reference of 16-bit g rows
+// (zero without one), which the stored bits are measured from.
+constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '3'};
 constexpr size_t kCkptHeader = 24;
 struct CkptCase {
     int nx, ny, prec, pitch;
     long long buf_bytes, macro_bytes;
+    double gs0, gsk;
 };
 constexpr size_t kCkptCase = sizeof(CkptCase);
-static_assert(kCkptCase == 32, "checkpoint case record is 32 bytes");
+static_assert(kCkptCase == 48, "checkpoint case record is 48 bytes");
 
 CkptCase ckpt_case(const lbm_ctx* c, size_t k)
 {
     const auto& h = c->H[k];
-    return CkptCase{h.nx, h.ny, c->prec, h.L.pitch, (long long)h.L.buf_bytes, (long long)h.L.macro_bytes};
+    return CkptCase{h.nx, h.ny, c->prec, h.L.pitch, (long long)h.L.buf_bytes, (long long)h.L.macro_bytes,
+                    c->P[k].cd.gs0, c->P[k].cd.gsk};
 }
+
+// The stochastic-rounding step counter a case starts from at init: the
+// context's step count after the init (a single case restarts at t = 0).
+unsigned init_tick(const lbm_ctx* c) { return unsigned(c->P.size() == 1 ? 0 : c->t); }
 
 // Enqueues n step launches starting from buffer `parity` (no host waits).
 int enqueue_steps(lbm_ctx* c, long long n, int parity)
@@ -804,6 +835,7 @@ __global__ void fill_doubles(double* __restrict__ p, long long n, double v)
 }
 
 __global__ void clear_flag(int* flag) { *flag = 0; }
+__global__ void set_word(unsigned* p, unsigned v) { *p = v; }
 
 namespace {
 
@@ -896,7 +928,8 @@ lbm_status lbm_case_init(lbm_ctx* c, int k, const double* rho, const double* ux,
     if (e == hipSuccess) e = hipMemsetAsync(P.flag, 0, sizeof(int), c->stream);
     int rc = 0;
     if (e == hipSuccess)
-        rc = lbm::launch_init(c->prec, c->d_P, k, (long long)nn, static_cast<const double*>(d), c->parity, c->stream);
+        rc = lbm::launch_init(c->prec, c->d_P, k, (long long)nn, static_cast<const double*>(d), c->parity,
+                              init_tick(c), c->stream);
     if (e == hipSuccess && rc == 0) e = hipStreamSynchronize(c->stream);
     (void)hipFree(d);
     if (e != hipSuccess) return hip_fail(c, e, "lbm_init");
@@ -944,7 +977,7 @@ lbm_status lbm_case_init_static(lbm_ctx* c, int k, const double* rho, const doub
     }
     hipLaunchKernelGGL(clear_flag, dim3(1), dim3(1), 0, c->stream, P.flag);
     HIP_TRY(c, hipGetLastError());
-    const int rc = lbm::launch_init(c->prec, c->d_P, k, nn, d, c->parity, c->stream);
+    const int rc = lbm::launch_init(c->prec, c->d_P, k, nn, d, c->parity, init_tick(c), c->stream);
     if (rc != 0) return hip_fail(c, hipError_t(rc), "init launch");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->H[k].inited = true;
@@ -1296,6 +1329,8 @@ lbm_status lbm_load(lbm_ctx* c, const void* host, size_t bytes)
         HIP_TRY(c, hipMemcpyAsync(h.base + 2 * h.L.buf_bytes, o, h.L.macro_bytes, hipMemcpyHostToDevice, c->stream));
         o += h.L.macro_bytes;
         HIP_TRY(c, hipMemsetAsync(c->P[k].flag, 0, sizeof(int), c->stream));
+        hipLaunchKernelGGL(set_word, dim3(1), dim3(1), 0, c->stream, c->P[k].tick + c->parity, unsigned(hdr[0]));
+        HIP_TRY(c, hipGetLastError());
         h.inited = true;
         h.diverged_at = -1;
     }
@@ -1355,3 +1390,16 @@ void lbm_destroy(lbm_ctx* c)
 }
 
 }  // extern "C"
+
+unsigned lbm_rounding_byte(int prec, int x, int y, unsigned t, int q)
+{
+    if (q < 0 || q > 17) return 0u;
+    if (prec == LBM_FP16S) return lbm::sr::byte_at(x, y, t, q);
+    if (prec == LBM_F32G16 && q >= 9) return lbm::sr::byte_at(x, y, t, q - 9);
+    return 0u;
+}
+
+float lbm_round_half_stochastic(float v, unsigned u)
+{
+    return __half2float(__float2half_rn(lbm::round_stochastic_half(v, u & 0xFFu)));
+}

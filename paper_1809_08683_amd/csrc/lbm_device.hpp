@@ -13,6 +13,7 @@
 #include <stdint.h>
 
 #include "lbm_params.hpp"
+#include "lbm_rounding.hpp"
 
 namespace lbm {
 
@@ -616,6 +617,8 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes)
 
 template <> struct Store<double> {
     using C = double;
+    static __device__ __forceinline__ void store_sr(double* p, double v, unsigned) { store(p, v); }
+    static __device__ __forceinline__ void bstore_sr(rsrc_t r, int vo, int so, double v, unsigned) { bstore(r, vo, so, v); }
     static __device__ __forceinline__ double load(const double* p) { return *p; }
     static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
     static __device__ __forceinline__ double bload(rsrc_t r, int vo, int so)
@@ -630,6 +633,8 @@ template <> struct Store<double> {
 };
 template <> struct Store<float> {
     using C = float;
+    static __device__ __forceinline__ void store_sr(float* p, float v, unsigned) { store(p, v); }
+    static __device__ __forceinline__ void bstore_sr(rsrc_t r, int vo, int so, float v, unsigned) { bstore(r, vo, so, v); }
     static __device__ __forceinline__ float load(const float* p) { return *p; }
     static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
     static __device__ __forceinline__ float bload(rsrc_t r, int vo, int so)
@@ -643,6 +648,12 @@ template <> struct Store<float> {
 };
 template <> struct Store<__half> {
     using C = float;
+    // stochastic rounding with the random byte u (lbm_rounding.hpp)
+    static __device__ __forceinline__ void store_sr(__half* p, float v, unsigned u) { store(p, round_stochastic_half(v, u)); }
+    static __device__ __forceinline__ void bstore_sr(rsrc_t r, int vo, int so, float v, unsigned u)
+    {
+        bstore(r, vo, so, round_stochastic_half(v, u));
+    }
     static __device__ __forceinline__ float load(const __half* p)
     {
         const unsigned short b = *reinterpret_cast<const unsigned short*>(p);

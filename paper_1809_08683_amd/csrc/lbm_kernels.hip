@@ -161,13 +161,13 @@ int step_shape(int prec, int variant, StepShape* out)
 }
 
 int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
-                int parity, hipStream_t stream)
+                int parity, unsigned t0, hipStream_t stream)
 {
     switch (prec) {
-    case PREC_F64: return launch_init_f64(d_cases, case_id, nodes, d_fields, parity, stream);
-    case PREC_F32: return launch_init_f32(d_cases, case_id, nodes, d_fields, parity, stream);
-    case PREC_F32G16: return launch_init_f32g16(d_cases, case_id, nodes, d_fields, parity, stream);
-    default: return launch_init_f16(d_cases, case_id, nodes, d_fields, parity, stream);
+    case PREC_F64: return launch_init_f64(d_cases, case_id, nodes, d_fields, parity, t0, stream);
+    case PREC_F32: return launch_init_f32(d_cases, case_id, nodes, d_fields, parity, t0, stream);
+    case PREC_F32G16: return launch_init_f32g16(d_cases, case_id, nodes, d_fields, parity, t0, stream);
+    default: return launch_init_f16(d_cases, case_id, nodes, d_fields, parity, t0, stream);
     }
 }
 

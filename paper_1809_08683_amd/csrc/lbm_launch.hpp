@@ -22,8 +22,9 @@ struct StepShape {
 int launch_step(int prec, int variant, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
                 int export_macros, hipStream_t stream);
 int step_shape(int prec, int variant, StepShape* out);
+// t0: the context's step count, the start of the case's stochastic-rounding step counter
 int launch_init(int prec, const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,
-                int parity, hipStream_t stream);
+                int parity, unsigned t0, hipStream_t stream);
 int launch_totals(const CaseParams* d_cases, int case_id, double* d_partial, int nblocks, double* d_out,
                   hipStream_t stream);
 int launch_nusselt(const CaseParams* d_cases, int case_id, int side, double* d_out, hipStream_t stream);
@@ -34,7 +35,7 @@ int launch_copy(const void* src, void* dst, long long bytes, hipStream_t stream)
                            int parity, int export_macros, hipStream_t stream);                               \
     int step_shape_##NAME(int variant, StepShape* out);                                                      \
     int launch_init_##NAME(const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,  \
-                           int parity, hipStream_t stream);
+                           int parity, unsigned t0, hipStream_t stream);
 LBM_DECLARE_FORMAT(f64)
 LBM_DECLARE_FORMAT(f32)
 LBM_DECLARE_FORMAT(f16)

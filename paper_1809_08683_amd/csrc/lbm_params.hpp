@@ -24,6 +24,12 @@ struct Coef {
     double side_T[4];
     // rest state (rho0, u = 0, T0) the stored DFs are measured from
     double rho0_d, T0_d, p0_d, rhoE0_d;   // p_EOS(rho0, T0), rho0 C_v T0
+    // Reference of 16-bit g rows (FP32 f + FP16 g and FP16S): the stored g of
+    // column x is measured from the rest equilibrium of the conduction state
+    // between two Dirichlet x-walls, which differs from the rest state above
+    // by g_ref - g_rest = v_q s(x) with s(x) = gs0 + gsk x = rho0 C_p (T_ref(x) - T0).
+    // Zero when the case has no such reference.
+    C gs0, gsk;
     double R_d, a_d, b_d, bcs_d;           // EOS constants for FP64 evaluation
 };
 
@@ -46,6 +52,7 @@ struct CaseParams {
     void* buf[2];              // ping-pong DF buffers: (ny + 2) row blocks of 18 DF rows (f then g)
     double* macro;             // [5][ny][nx]: rho, ux, uy, T, p (written on export steps)
     int* flag;                 // divergence flag of this case
+    unsigned* tick;            // step counters of the stochastic rounding: a step reads [parity], writes [parity ^ 1]
     Coef<double> cd;
     Coef<float> cf;
 };

@@ -204,16 +204,73 @@ template <typename Fm> __device__ __forceinline__ typename Fm::C load_df(const c
     using G = typename Fm::G;
     return q < 9 ? Store<F>::load(reinterpret_cast<const F*>(buf + off)) : Store<G>::load(reinterpret_cast<const G*>(buf + off));
 }
-template <typename Fm> __device__ __forceinline__ void store_df(char* buf, int q, long long off, typename Fm::C v)
+// store of DF row q (0..17) with the random byte u of its stochastic rounding
+template <typename Fm> __device__ __forceinline__ void store_df(char* buf, int q, long long off, typename Fm::C v,
+                                                                unsigned u)
 {
     using F = typename Fm::F;
     using G = typename Fm::G;
-    if (q < 9) Store<F>::store(reinterpret_cast<F*>(buf + off), v);
-    else Store<G>::store(reinterpret_cast<G*>(buf + off), v);
+    if (q < 9) Store<F>::store_sr(reinterpret_cast<F*>(buf + off), v, u);
+    else Store<G>::store_sr(reinterpret_cast<G*>(buf + off), v, u);
 }
 template <typename Fm> __device__ __forceinline__ long long slot_bytes(int q, int slot)
 {
     return (long long)slot * (q < 9 ? Fm::EF : Fm::EG);
+}
+
+// Reference of the 16-bit g rows (FP32 f + FP16 g and FP16S storage).  In a cavity
+// between Dirichlet x-walls the rest deviation g - g_rest is O(Delta T)
+// everywhere, and the FP16 rounding of it limits the heat flux at the walls.
+// The g rows of that format therefore store g - g_ref(x), where g_ref is the
+// rest equilibrium of the conduction state: T_ref linear between the wall
+// temperatures and rho_ref T_ref = rho0 T0 (uniform ideal-gas pressure).  At
+// rest, n^eq (Sec. 2.2) depends on the state only through rho E, which is
+// uniform there, and rho0 C_p T in rows 1 and 2, so
+//   g_ref - g_rest = M^-1 (0, 4 + gamma1, -4 + gamma2, 0, ..., 0) s(x),
+//   s(x) = rho0 C_p (T_ref(x) - T0) = gs0 + gsk x,
+// an offset v_q s(x) per DF that costs no stored bytes.  Every store of a g
+// row subtracts the offset of the column it is stored in and every load adds
+// it back, so the reference never changes what the scheme computes, only
+// what the 16-bit rows round.  The interior march applies it to the moments
+// instead: a pull reads DF q from column x - e_qx, and
+//   M [v_q s(x - e_qx)]_q = s(x) (0, 4 + gamma1, -4 + gamma2, 0, ...)
+//                           - gsk (0, 0, 0, sum_q e_qx^2 v_q, sum_q M_4q e_qx v_q, 0, ...).
+namespace gref {
+constexpr double a1 = (4.0 + mc::gamma1) / 36.0, a2 = (-4.0 + mc::gamma2) / 36.0;   // M^-1 = M^T diag(.., 1/36, 1/36, ..)
+constexpr double v_rest = -4.0 * a1 + 4.0 * a2;
+constexpr double v_axis = -a1 - 2.0 * a2;
+constexpr double v_diag = 2.0 * a1 + a2;
+constexpr double m1 = 4.0 + mc::gamma1, m2 = -4.0 + mc::gamma2;   // rows 1, 2 of M v
+constexpr double m3 = 2.0 * v_axis + 4.0 * v_diag;                 // sum_q e_qx^2 v_q
+constexpr double m4 = -4.0 * v_axis + 4.0 * v_diag;                // sum_q M_4q e_qx v_q
+static_assert(v_rest + 4.0 * v_axis + 4.0 * v_diag == 0.0, "the reference leaves n_0 unchanged");
+}  // namespace gref
+template <typename Fm> constexpr bool has_gref = Fm::EG == 2;
+
+// Stochastic rounding (lbm_rounding.hpp) of the format's 16-bit rows.
+namespace sr {
+template <typename Fm> constexpr bool used = Fm::EF == 2 || Fm::EG == 2;
+// index of DF row q (0..17) among the 16-bit rows of the format (negative: not 16-bit)
+template <typename Fm> constexpr int index(int q) { return Fm::EF == 2 ? q : q - 9; }
+// random byte of DF row q stored at (x, y) (wrapped on a periodic axis) in step t
+template <typename Fm> __device__ __forceinline__ unsigned byte_of(int x, int y, unsigned t, int q)
+{
+    if constexpr (!used<Fm>) return 0u;
+    if ((q < 9 ? Fm::EF : Fm::EG) != 2) return 0u;
+    return byte_at(x, y, t, index<Fm>(q));
+}
+}  // namespace sr
+template <typename C> __device__ __forceinline__ C gref_v(int q)
+{
+    return C(q == 0 ? gref::v_rest : (q <= 4 ? gref::v_axis : gref::v_diag));
+}
+// offset of DF q stored in column col
+template <typename Fm> __device__ __forceinline__ typename Fm::C gref_offset(const CaseParams& P, int q, int col)
+{
+    using C = typename Fm::C;
+    if constexpr (!has_gref<Fm>) return C(0);
+    const Coef<C>& K = coef<C>(P);
+    return gref_v<C>(q) * (K.gs0 + K.gsk * C(col));
 }
 
 // side indices of a node: x-side (0/1) or -1, y-side (2/3) or -1
@@ -257,6 +314,7 @@ __device__ __forceinline__ void pull_node(const CaseParams& P, const char* src, 
         const int slot = col_slot(P, sx);
         f[q] = load_df<Fm>(src, q, row_byte<Fm>(P, q, sy) + slot_bytes<Fm>(q, slot));
         g[q] = load_df<Fm>(src, 9 + q, row_byte<Fm>(P, 9 + q, sy) + slot_bytes<Fm>(9 + q, slot));
+        if constexpr (has_gref<Fm>) g[q] += gref_offset<Fm>(P, q, sx);
     }
     to_moments<C>(f, m);
     to_moments<C>(g, n);
@@ -265,13 +323,17 @@ __device__ __forceinline__ void pull_node(const CaseParams& P, const char* src, 
 // store the 18 DFs of node (x, y) into every slot that holds its column
 template <typename Fm>
 __device__ __forceinline__ void store_node(const CaseParams& P, char* dst, int x, int y,
-                                           const typename Fm::C fb[9], const typename Fm::C gb[9])
+                                           const typename Fm::C fb[9], const typename Fm::C gb[9], unsigned t)
 {
+    typename Fm::C gs[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) gs[q] = gb[q] - gref_offset<Fm>(P, q, x);
     for_each_slot(P, x, [&](int slot) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            store_df<Fm>(dst, q, row_byte<Fm>(P, q, y) + slot_bytes<Fm>(q, slot), fb[q]);
-            store_df<Fm>(dst, 9 + q, row_byte<Fm>(P, 9 + q, y) + slot_bytes<Fm>(9 + q, slot), gb[q]);
+            store_df<Fm>(dst, q, row_byte<Fm>(P, q, y) + slot_bytes<Fm>(q, slot), fb[q], sr::byte_of<Fm>(x, y, t, q));
+            store_df<Fm>(dst, 9 + q, row_byte<Fm>(P, 9 + q, y) + slot_bytes<Fm>(9 + q, slot), gs[q],
+                         sr::byte_of<Fm>(x, y, t, 9 + q));
         }
     });
 }
@@ -280,7 +342,7 @@ __device__ __forceinline__ void store_node(const CaseParams& P, char* dst, int x
 // ghost cells they reach, in the row of the opposite direction.
 template <typename Fm>
 __device__ __forceinline__ void store_ghosts(const CaseParams& P, char* dst, int x, int y,
-                                             const typename Fm::C fb[9], const typename Fm::C gb[9])
+                                             const typename Fm::C fb[9], const typename Fm::C gb[9], unsigned t)
 {
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
@@ -288,9 +350,12 @@ __device__ __forceinline__ void store_ghosts(const CaseParams& P, char* dst, int
         const bool out = (P.wall_x && (tx < 0 || tx >= P.nx)) || (P.wall_y && (ty < 0 || ty >= P.ny));
         if (out) {
             const int qf = OPPq(q), qg = 9 + OPPq(q);
+            const typename Fm::C gs = gb[q] - gref_offset<Fm>(P, OPPq(q), tx);
+            const int kx = wrap_axis(tx, P.nx, P.wall_x), ky = wrap_axis(ty, P.ny, P.wall_y);
+            const unsigned uf = sr::byte_of<Fm>(kx, ky, t, qf), ug = sr::byte_of<Fm>(kx, ky, t, qg);
             for_each_slot(P, tx, [&](int slot) {
-                store_df<Fm>(dst, qf, row_byte<Fm>(P, qf, ty) + slot_bytes<Fm>(qf, slot), fb[q]);
-                store_df<Fm>(dst, qg, row_byte<Fm>(P, qg, ty) + slot_bytes<Fm>(qg, slot), gb[q]);
+                store_df<Fm>(dst, qf, row_byte<Fm>(P, qf, ty) + slot_bytes<Fm>(qf, slot), fb[q], uf);
+                store_df<Fm>(dst, qg, row_byte<Fm>(P, qg, ty) + slot_bytes<Fm>(qg, slot), gs, ug);
             });
         }
     }
@@ -323,7 +388,9 @@ __device__ __forceinline__ void export_node(const CaseParams& P, int x, int y, c
 //   H = n - n^eq + Q_m/2, Htil = (I - L/2) H (App. C steps 1-3),
 //   nbar = 2 n^eq - n + 2 Htil + Y [(m + mbar)/2 - m^eq] (eq. LBE.T.c,
 //   App. C step 4), conserved row nbar_0 = n_0 + q_e.
-// The f and g post-collision deviations go to fb and gb.
+// The f and g post-collision deviations go to fb and gb; gb is taken
+// relative to the 16-bit reference of the node's column (sref, zero without
+// one).
 // ---------------------------------------------------------------------------
 // Whole-wavefront lane shifts by one lane (DPP wave_shr:1 / wave_shl:1):
 // lane l receives the value of lane l - 1 (from_left) or l + 1 (from_right);
@@ -386,6 +453,7 @@ template <typename C, bool XW = false>
 __device__ __forceinline__ void collide_interior(const CaseParams& P, const Coef<C>& K, const NodeState<C>& s,
                                                  const C m[9], const C n[9],
                                                  C gr_x, C gr_y, C gp_x, C gp_y, C fb[9], C gb[9],
+                                                 C sref,
                                                  const XWallLane& xl = XWallLane{false, false, false})
 {
     Rates<C> r;
@@ -480,6 +548,9 @@ __device__ __forceinline__ void collide_interior(const CaseParams& P, const Coef
         nb[4] -= z3;
         nb[5] += z5;
         nb[6] -= z5;
+        // stored g: measured from the 16-bit rows' reference of this column
+        nb[1] -= C(gref::m1) * sref;
+        nb[2] -= C(gref::m2) * sref;
         from_moments<C>(nb, gb);
     }
 }
@@ -529,7 +600,8 @@ __device__ __forceinline__ int stored_row(int v, int n, int walled)
 // stores of row y.
 template <typename Fm, bool EXPORT, bool XW>
 __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkItem w, const char* __restrict__ src_in,
-                                              char* __restrict__ dst_in, typename Fm::C* __restrict__ park)
+                                              char* __restrict__ dst_in, typename Fm::C* __restrict__ park,
+                                              unsigned tk)
 {
     const char* __restrict__ src = uniform_ptr(src_in);
     char* __restrict__ dst = uniform_ptr(dst_in);
@@ -549,6 +621,17 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     const int cn = wall_x ? min(max(c, 0), nx - 1) : wrap_axis(c, nx, 0);
     const bool regular = c == cn || !wall_x;
     const int sx = side_x(P, cn);
+    const unsigned sx_seed = sr::seed_x(cn);   // column part of the stochastic-rounding seed
+    // reference of 16-bit g rows: s at this lane's node column (its moments
+    // in rows 1 and 2 are m1 s and m2 s) and the part that a pull from the
+    // neighbouring columns adds to rows 3 and 4 (wave-uniform); zero without
+    // a reference
+    C sref = C(0), gr3 = C(0), gr4 = C(0);
+    if constexpr (has_gref<Fm>) {
+        sref = K.gs0 + K.gsk * C(cn);
+        gr3 = C(-gref::m3) * K.gsk;
+        gr4 = C(-gref::m4) * K.gsk;
+    }
     // byte offset of the slot a pull along e_x reads: inside the own region
     // for source columns X - 1 .. X + 60 (own columns and the two copies, or
     // the wall and ghost slots on a walled side), the owning slot otherwise
@@ -601,6 +684,12 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     auto row_state = [&](int yy, const C f[9], const C g[9], C dm[9], C dn[9], NodeState<C>& st) {
         to_moments<C>(f, dm);
         to_moments<C>(g, dn);
+        if constexpr (has_gref<Fm>) {
+            dn[1] += C(gref::m1) * sref;
+            dn[2] += C(gref::m2) * sref;
+            dn[3] += gr3;
+            if constexpr (gref::m4 != 0.0) dn[4] += gr4;
+        }
         const int sy = side_y(P, stored_row(yy, ny, wall_y) - 1);
         if (sy >= 0 || !Tuning<Fm>::edge_select) return node_state<C>(P, K, sx, sy, dm, dn[0], st);
         if (edge) {
@@ -685,15 +774,37 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
             const C wr_y = fd * ((s_n.drho - rho_b) * C(0.5));
             const C wp_y = fd * ((s_n.dp - p_b) * C(0.5));
             collide_interior<C, true>(P, K, s_c, m_c, n_c, xl.wall ? wr_x : gr_x, xl.wall ? wr_y : gr_y,
-                                      xl.wall ? wp_x : gp_x, xl.wall ? wp_y : gp_y, fb, gb, xl);
+                                      xl.wall ? wp_x : gp_x, xl.wall ? wp_y : gp_y, fb, gb, sref, xl);
         } else {
-            collide_interior<C>(P, K, s_c, m_c, n_c, gr_x, gr_y, gp_x, gp_y, fb, gb);
+            collide_interior<C>(P, K, s_c, m_c, n_c, gr_x, gr_y, gp_x, gp_y, fb, gb, sref);
         }
         const rsrc_t ro = make_rsrc(dst + (long long)(y + 1) * blk, blk_bytes);
+        if constexpr (sr::used<Fm>) {
+            // the f rows, then the g rows, so that few random words are live at once
+            unsigned w = sr::mix(sx_seed ^ sr::seed_yt(y, tk));   // word 0 of this lane's node
+            int wk = 0;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            Store<F>::bstore(ro, vf_out, q * frow_bytes, fb[q]);
-            Store<G>::bstore(ro, vg_out, g_base + q * grow_bytes, gb[q]);
+            for (int j = 0; j < 18; ++j) {
+                const int q = j < 9 ? j : j - 9;
+                const int i = sr::index<Fm>(j);
+                if (i < 0) {
+                    Store<F>::bstore(ro, vf_out, q * frow_bytes, fb[q]);
+                    continue;
+                }
+                if ((i >> 2) != wk) {
+                    w = sr::xorshift(w);
+                    wk = i >> 2;
+                }
+                const unsigned u = (w >> (8 * (i & 3))) & 0xFFu;
+                if (j < 9) Store<F>::bstore_sr(ro, vf_out, q * frow_bytes, fb[q], u);
+                else Store<G>::bstore_sr(ro, vg_out, g_base + q * grow_bytes, gb[q], u);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                Store<F>::bstore(ro, vf_out, q * frow_bytes, fb[q]);
+                Store<G>::bstore(ro, vg_out, g_base + q * grow_bytes, gb[q]);
+            }
         }
         if constexpr (XW) {
             // the DFs a wall node sends out of the domain go to the ghost
@@ -702,25 +813,35 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
             const rsrc_t rp = make_rsrc(dst + (long long)stored_row(y + 1, ny, wall_y) * blk, blk_bytes);
             const rsrc_t rm = make_rsrc(dst + (long long)stored_row(y - 1, ny, wall_y) * blk, blk_bytes);
             const int gsl = region + (xl.left ? lane - 1 : lane + 1);
+            // gb is relative to the 16-bit reference of the wall column; the
+            // ghost column next to it (x -/+ 1) has offsets v_q gsk higher / lower
+            C gka = C(0), gkd = C(0);
+            if constexpr (has_gref<Fm>) {
+                gka = C(gref::v_axis) * K.gsk;
+                gkd = C(gref::v_diag) * K.gsk;
+            }
+            // random bytes of the ghost slots (column x -/+ 1, rows y, y + 1, y - 1)
+            const int gcol = xl.left ? c - 1 : c + 1;
+            const int yp = wrap_axis(y + 1, ny, wall_y), ym = wrap_axis(y - 1, ny, wall_y);
             if (has_left) {
                 // left wall: q = 3, 6, 7 leave as 1, 8, 5 in rows y, y + 1, y - 1
                 const int vf = xl.wall && xl.left ? gsl * EF : kDropOffset, vg = xl.wall && xl.left ? gsl * EG : kDropOffset;
-                Store<F>::bstore(ro, vf, 1 * frow_bytes, fb[3]);
-                Store<G>::bstore(ro, vg, g_base + 1 * grow_bytes, gb[3]);
-                Store<F>::bstore(rp, vf, 8 * frow_bytes, fb[6]);
-                Store<G>::bstore(rp, vg, g_base + 8 * grow_bytes, gb[6]);
-                Store<F>::bstore(rm, vf, 5 * frow_bytes, fb[7]);
-                Store<G>::bstore(rm, vg, g_base + 5 * grow_bytes, gb[7]);
+                Store<F>::bstore_sr(ro, vf, 1 * frow_bytes, fb[3], sr::byte_of<Fm>(gcol, y, tk, 1));
+                Store<G>::bstore_sr(ro, vg, g_base + 1 * grow_bytes, gb[3] + gka, sr::byte_of<Fm>(gcol, y, tk, 10));
+                Store<F>::bstore_sr(rp, vf, 8 * frow_bytes, fb[6], sr::byte_of<Fm>(gcol, yp, tk, 8));
+                Store<G>::bstore_sr(rp, vg, g_base + 8 * grow_bytes, gb[6] + gkd, sr::byte_of<Fm>(gcol, yp, tk, 17));
+                Store<F>::bstore_sr(rm, vf, 5 * frow_bytes, fb[7], sr::byte_of<Fm>(gcol, ym, tk, 5));
+                Store<G>::bstore_sr(rm, vg, g_base + 5 * grow_bytes, gb[7] + gkd, sr::byte_of<Fm>(gcol, ym, tk, 14));
             }
             if (has_right) {
                 // right wall: q = 1, 5, 8 leave as 3, 7, 6 in rows y, y + 1, y - 1
                 const int vf = xl.wall && !xl.left ? gsl * EF : kDropOffset, vg = xl.wall && !xl.left ? gsl * EG : kDropOffset;
-                Store<F>::bstore(ro, vf, 3 * frow_bytes, fb[1]);
-                Store<G>::bstore(ro, vg, g_base + 3 * grow_bytes, gb[1]);
-                Store<F>::bstore(rp, vf, 7 * frow_bytes, fb[5]);
-                Store<G>::bstore(rp, vg, g_base + 7 * grow_bytes, gb[5]);
-                Store<F>::bstore(rm, vf, 6 * frow_bytes, fb[8]);
-                Store<G>::bstore(rm, vg, g_base + 6 * grow_bytes, gb[8]);
+                Store<F>::bstore_sr(ro, vf, 3 * frow_bytes, fb[1], sr::byte_of<Fm>(gcol, y, tk, 3));
+                Store<G>::bstore_sr(ro, vg, g_base + 3 * grow_bytes, gb[1] - gka, sr::byte_of<Fm>(gcol, y, tk, 12));
+                Store<F>::bstore_sr(rp, vf, 7 * frow_bytes, fb[5], sr::byte_of<Fm>(gcol, yp, tk, 7));
+                Store<G>::bstore_sr(rp, vg, g_base + 7 * grow_bytes, gb[5] - gkd, sr::byte_of<Fm>(gcol, yp, tk, 16));
+                Store<F>::bstore_sr(rm, vf, 6 * frow_bytes, fb[8], sr::byte_of<Fm>(gcol, ym, tk, 6));
+                Store<G>::bstore_sr(rm, vg, g_base + 6 * grow_bytes, gb[8] - gkd, sr::byte_of<Fm>(gcol, ym, tk, 15));
             }
         }
         if (EXPORT && (out_lane || xl.wall)) export_node<C>(P, c, y, s_c, K.T0_d + double(s_c.dT));
@@ -833,7 +954,7 @@ __device__ __forceinline__ void tilde_at(const CaseParams& P, const char* src, i
 // One wall node (index i of the case's wall-node enumeration) per lane.
 template <typename Fmt, bool EXPORT>
 __device__ __forceinline__ void wall_node(const CaseParams& P, int i, const char* __restrict__ src,
-                                          char* __restrict__ dst)
+                                          char* __restrict__ dst, unsigned tk)
 {
     using C = typename Fmt::C;
     const Coef<C>& K = coef<C>(P);
@@ -897,19 +1018,19 @@ __device__ __forceinline__ void wall_node(const CaseParams& P, int i, const char
     post_collision<C>(s, r, P.cubic, meq, Fm, N, Zm, neq, Qm, Hm, Ht, gr_x, gr_y, gp_x, gp_y, mb, nb);
     from_moments<C>(mb, fb);
     from_moments<C>(nb, gb);
-    store_node<Fmt>(P, dst, xb, yb, fb, gb);
-    store_ghosts<Fmt>(P, dst, xb, yb, fb, gb);
+    store_node<Fmt>(P, dst, xb, yb, fb, gb, tk);
+    store_ghosts<Fmt>(P, dst, xb, yb, fb, gb, tk);
     if (EXPORT) export_node<C>(P, xb, yb, s, T_d);
 }
 
 // wall item: wall nodes [x0, x0 + len), 64 at a time
 template <typename Fmt, bool EXPORT>
 __device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w, const char* __restrict__ src,
-                                          char* __restrict__ dst)
+                                          char* __restrict__ dst, unsigned tk)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     for (int base = 0; base < w.len; base += WAVE)
-        if (base + lane < w.len) wall_node<Fmt, EXPORT>(P, w.x0 + base + lane, src, dst);
+        if (base + lane < w.len) wall_node<Fmt, EXPORT>(P, w.x0 + base + lane, src, dst, tk);
 }
 
 // ---------------------------------------------------------------------------
@@ -942,6 +1063,13 @@ __attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
     if (w.kind == 2) return;
     progress_priority<Fm>(0, 1);
     const CaseParams& P = *(const CaseParams*)(((const __attribute__((address_space(4))) CaseParams*)cases) + w.case_id);
+    // step counter of the stochastic rounding: every wavefront of the case
+    // reads this step's value and writes the next step's (the same value)
+    unsigned tk = 0u;
+    if constexpr (sr::used<Fm>) {
+        tk = __builtin_amdgcn_readfirstlane(*as_global<unsigned>(P.tick + parity));
+        if ((threadIdx.x & (WAVE - 1)) == 0) *as_global_mut<unsigned>(P.tick + (parity ^ 1)) = tk + 1u;
+    }
     if (w.kind == 0) {
         const char* src = static_cast<const char*>(P.buf[parity]);
         char* dst = static_cast<char*>(P.buf[parity ^ 1]);
@@ -952,14 +1080,14 @@ __attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
         if constexpr (Tuning<Fm>::xw_strips) xw = P.wall_x && (w.x0 == P.xlo || w.x0 + STRIP_COLS >= P.nx - 1);
         if constexpr (Tuning<Fm>::xw_strips) {
             if (xw) {
-                interior_item<Fm, EXPORT, true>(P, w, src, dst, park);
+                interior_item<Fm, EXPORT, true>(P, w, src, dst, park, tk);
                 return;
             }
         }
-        interior_item<Fm, EXPORT, false>(P, w, src, dst, park);
+        interior_item<Fm, EXPORT, false>(P, w, src, dst, park, tk);
     }
     else
-        wall_item<Fm, EXPORT>(P, w, static_cast<const char*>(P.buf[parity]), static_cast<char*>(P.buf[parity ^ 1]));
+        wall_item<Fm, EXPORT>(P, w, static_cast<const char*>(P.buf[parity]), static_cast<char*>(P.buf[parity ^ 1]), tk);
 }
 
 // ---------------------------------------------------------------------------
@@ -989,12 +1117,13 @@ __device__ __forceinline__ void init_rho_p(const CaseParams& P, const Coef<C>& K
 
 template <typename Fmt>
 __global__ __launch_bounds__(256) void init_kernel(const CaseParams* __restrict__ cases, int case_id,
-                                                   const double* __restrict__ fld, int parity)
+                                                   const double* __restrict__ fld, int parity, unsigned t0)
 {
     using C = typename Fmt::C;
     const CaseParams& P = cases[case_id];
     const Coef<C>& K = coef<C>(P);
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid == 0) P.tick[parity] = t0;   // step counter of the stochastic rounding
     if (gid >= (long long)P.nx * P.ny) return;
     const int x = int(gid % P.nx), y = int(gid / P.nx);
     NodeState<C> s;
@@ -1052,8 +1181,8 @@ __global__ __launch_bounds__(256) void init_kernel(const CaseParams* __restrict_
     from_moments<C>(mb, fb);
     from_moments<C>(nb, gb);
     char* dst = static_cast<char*>(P.buf[parity]);
-    store_node<Fmt>(P, dst, x, y, fb, gb);
-    if (sx >= 0 || sy >= 0) store_ghosts<Fmt>(P, dst, x, y, fb, gb);
+    store_node<Fmt>(P, dst, x, y, fb, gb, t0);
+    if (sx >= 0 || sy >= 0) store_ghosts<Fmt>(P, dst, x, y, fb, gb, t0);
     export_node<C>(P, x, y, s, T_d);
 }
 
@@ -1118,10 +1247,10 @@ int step_shape_fmt(int variant, StepShape* out)
 
 template <typename Base>
 int launch_init_fmt(const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields, int parity,
-                    hipStream_t stream)
+                    unsigned t0, hipStream_t stream)
 {
     const dim3 grid(unsigned((nodes + 255) / 256)), block(256);
-    hipLaunchKernelGGL((init_kernel<Base>), grid, block, 0, stream, d_cases, case_id, d_fields, parity);
+    hipLaunchKernelGGL((init_kernel<Base>), grid, block, 0, stream, d_cases, case_id, d_fields, parity, t0);
     return int(hipGetLastError());
 }
 
@@ -1134,9 +1263,9 @@ int launch_init_fmt(const CaseParams* d_cases, int case_id, long long nodes, con
     }                                                                                                        \
     int step_shape_##NAME(int variant, StepShape* out) { return step_shape_fmt<FMT>(variant, out); }         \
     int launch_init_##NAME(const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,  \
-                           int parity, hipStream_t stream)                                                   \
+                           int parity, unsigned t0, hipStream_t stream)                                      \
     {                                                                                                        \
-        return launch_init_fmt<FMT>(d_cases, case_id, nodes, d_fields, parity, stream);                      \
+        return launch_init_fmt<FMT>(d_cases, case_id, nodes, d_fields, parity, t0, stream);                  \
     }
 
 }  // namespace lbm

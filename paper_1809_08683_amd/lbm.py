@@ -124,6 +124,8 @@ def load_library():
         "lbm_batch_nusselt": ([vp, C.c_int, _D, C.POINTER(C.c_int)], C.c_int),
         "lbm_work_items": ([vp], C.c_longlong),
         "lbm_copy_bandwidth": ([C.c_size_t, C.c_int, vp, _D, _D], C.c_int),
+        "lbm_rounding_byte": ([C.c_int, C.c_int, C.c_int, C.c_uint, C.c_int], C.c_uint),
+        "lbm_round_half_stochastic": ([C.c_float, C.c_uint], C.c_float),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -140,7 +142,7 @@ def exported_symbols():
             "lbm_save", "lbm_load", "lbm_time", "lbm_last_error", "lbm_destroy",
             "lbm_batch_create", "lbm_batch_size", "lbm_case_init", "lbm_case_init_static", "lbm_case_macros",
             "lbm_case_nusselt", "lbm_case_totals", "lbm_batch_flags", "lbm_batch_step", "lbm_batch_nusselt", "lbm_work_items",
-            "lbm_copy_bandwidth"]
+            "lbm_copy_bandwidth", "lbm_rounding_byte", "lbm_round_half_stochastic"]
 
 
 def copy_bandwidth(nbytes: int, iters: int = 20, stream=None):
@@ -151,6 +153,18 @@ def copy_bandwidth(nbytes: int, iters: int = 20, stream=None):
     if rc != OK:
         raise LBMError(rc, "lbm_copy_bandwidth")
     return g.value, ms.value
+
+
+def rounding_byte(prec, x: int, y: int, t: int, q: int) -> int:
+    """Random byte (0-255) of the stochastic rounding of DF row q at node
+    (x, y) in step t (host computation with the kernels' code)."""
+    return int(load_library().lbm_rounding_byte(PREC[prec] if isinstance(prec, str) else int(prec),
+                                                 int(x), int(y), int(t) & 0xFFFFFFFF, int(q)))
+
+
+def round_half_stochastic(v: float, u: int) -> float:
+    """The FP16 value (as float) that v is stored as with random byte u."""
+    return float(load_library().lbm_round_half_stochastic(float(v), int(u)))
 
 
 def _ptr(a):

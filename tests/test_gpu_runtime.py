@@ -68,12 +68,13 @@ def test_every_launch_configuration_gives_the_same_state(prec):
             b.close()
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("prec", ["f32", "f64", "f16s", "f32g16"])
 def test_graph_replay_equals_plain_launches(prec):
     """The captured graph of n steps is replayed several times with eager
     work (macro and totals reads) in between; every replay matches plain
     stepping, for an even and an odd n (the odd graph starts from either
-    buffer)."""
+    buffer).  In the 16-bit formats this also checks the device step
+    counter of the stochastic rounding, which the replays advance."""
     ref, cases = _batch(prec)
     g, _ = _batch(prec)
     for n in (6, 6, 5, 5, 5, 6):
