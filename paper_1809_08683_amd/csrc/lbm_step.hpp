@@ -644,7 +644,6 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     // per-lane byte offsets in f rows and in g rows (the same when both use one type)
     const int vf0 = sl0 * EF, vf1 = sl1 * EF, vf2 = sl2 * EF;
     const int vg0 = sl0 * EG, vg1 = sl1 * EG, vg2 = sl2 * EG;
-    // slots this lane stores: all but the wall and ghost slots of a walled side
     // x-wall nodes collided by this strip (XW: the case has them in its
     // strips and this strip holds the column 0 or nx - 1 on a lane 1..62)
     XWallLane xl{false, false, P.extrap_order == 2};
@@ -654,7 +653,10 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     }
     // the strip holds the left / right wall column (wave-uniform)
     const bool has_left = XW && X == P.xlo, has_right = XW && X + STRIP_COLS >= nx - 1;
-    const bool keep = wall_x && (c == -1 || c == 0 || c == nx - 1 || c == nx) && !xl.wall;
+    // slots this lane stores: all but the wall and ghost slots of a walled
+    // side (unless the lane collides the wall node) and the slots past the
+    // ghost column of a ragged last strip, which nothing reads
+    const bool keep = wall_x && (c == -1 || c == 0 || c >= nx - 1) && !xl.wall;
     const int vf_out = keep ? kDropOffset : (region + lane) * EF;
     const int vg_out = keep ? kDropOffset : (region + lane) * EG;
     const bool out_lane = lane >= 2 && lane < 2 + STRIP_COLS && c < xhi;   // own nodes
