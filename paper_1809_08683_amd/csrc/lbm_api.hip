@@ -45,12 +45,15 @@ Layout layout_of(int nx, int ny, int prec)
 {
     Layout L;
     // enough 64-slot strip regions for the off-wall columns of either kind of
-    // x boundary (periodic needs ceil(nx / 60), walled ceil((nx - 2) / 60)),
-    // plus two regions that nothing reads or writes: with the longer row
-    // stride the rows a step touches at once fall on the HBM channels more
-    // evenly (0.5-2.6 % faster on a 2048^2 grid in every format, never
-    // slower; other pads ranged from -15 % to +4 % depending on the format).
-    L.pitch = ((nx + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS + 2) * lbm::REGION_SLOTS;
+    // x boundary (periodic needs ceil(nx / 62), walled ceil((nx - 2) / 62)),
+    // plus at least two regions that hold at most the right ghost column and,
+    // in the row's last slot, the left one, rounded up to an odd count: the
+    // row stride is then an odd multiple of a region, and the rows a step
+    // touches at once fall on the HBM channels more evenly (on the 2048^2
+    // cavity 36 regions ran FP32 3 % and FP64 4 % slower than 37; pads from 2
+    // to 11 regions spanned 4 % in FP32 and 10 % in FP64).
+    const int regions = (nx + lbm::STRIP_COLS - 1) / lbm::STRIP_COLS + 2;
+    L.pitch = (regions | 1) * lbm::REGION_SLOTS;
     L.plane = (long long)(ny + 2) * L.pitch;
     L.buf_bytes = round_up(size_t(9) * L.plane * (f_size(prec) + g_size(prec)), 256);
     L.macro_bytes = round_up(size_t(5) * nx * ny * sizeof(double), 256);
@@ -614,7 +617,7 @@ lbm_status read_flags(lbm_ctx* c, std::vector<int>& flags)
 // macro array.  lbm_load accepts a checkpoint only if every record equals the
 // context's own.  The record includes the reference of 16-bit g rows
 // (zero without one), which the stored bits are measured from.
-constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '3'};
+constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '4'};
 constexpr size_t kCkptHeader = 24;
 struct CkptCase {
     int nx, ny, prec, pitch;

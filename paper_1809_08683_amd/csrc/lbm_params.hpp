@@ -34,12 +34,13 @@ struct Coef {
 };
 
 // Columns are stored strip by strip: strip s owns the off-wall columns
-// [xlo + 60 s, xlo + 60 s + 60) and keeps them, with copies of two neighbour
-// columns, in a region of 64 slots: slot j holds column xlo + 60 s - 2 + j.
-// Slots 2..61 are the strip's own columns, slots 1 and 62 copies of the
-// neighbouring strips' edge columns (the left wall and ghost columns sit in
-// slots 1 and 0 of strip 0, the right ones after the last strip's columns).
-constexpr int STRIP_COLS = 60;
+// [xlo + 62 s, xlo + 62 s + 62) and keeps them in a region of 64 slots:
+// slot j holds column xlo + 62 s - 1 + j, so slots 1..62 are its own columns
+// and slots 0 and 63 (the neighbouring strips' edge columns) are not
+// written.  On a walled x axis the left wall column sits in slot 0 of strip
+// 0, the right wall and ghost columns after the last strip's columns, and
+// the left ghost column in the last slot of the row.
+constexpr int STRIP_COLS = 62;
 constexpr int REGION_SLOTS = 64;
 
 struct CaseParams {

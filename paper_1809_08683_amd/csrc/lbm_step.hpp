@@ -8,9 +8,8 @@
 // holds 18 rows of `pitch` elements, one per DF (f_0..f_8, g_0..g_8), so DF q
 // of node (x, y) sits at element ((y + 1) * 18 + q) * pitch + slot(x).  Along
 // a DF row the columns are kept in 64-slot strip regions (see CaseParams):
-// each interior wavefront stores whole, aligned regions, i.e. whole cache
-// lines, and the two columns next to a strip are kept as copies inside its
-// region, so that only the edge lanes read a neighbouring region.  The extra
+// each interior wavefront stores the 62 own slots of its region; its edge
+// lanes pull the neighbouring strips' edge columns from their regions.  The extra
 // stored rows, and slots 0-1 of the first region and the two slots after the
 // last column on walled sides, hold ghost cells: a wall node writes every
 // post-collision DF that would leave the domain into the ghost cell it would
@@ -123,7 +122,7 @@ struct Tuning<Variant<Base, V>> : Tuning<Base> {
 };
 static_assert(NUM_STEP_VARIANTS == 4, "variants 0-3 are defined above");
 
-static_assert(REGION_SLOTS == WAVE && STRIP_COLS == WAVE - 4, "one wavefront per strip region");
+static_assert(REGION_SLOTS == WAVE && STRIP_COLS == WAVE - 2, "one wavefront per strip region");
 
 #define EXq(q) ((q) == 1 || (q) == 5 || (q) == 8 ? 1 : ((q) == 3 || (q) == 6 || (q) == 7 ? -1 : 0))
 #define EYq(q) ((q) == 2 || (q) == 5 || (q) == 6 ? 1 : ((q) == 4 || (q) == 7 || (q) == 8 ? -1 : 0))
@@ -139,43 +138,22 @@ __device__ __forceinline__ int wrap_axis(int v, int n, int walled)
 __device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 // storage slot of column x in [-1, nx] (wrapped on a periodic axis) within a
-// stored DF row: the slot of its owning strip, or for the wall and ghost
-// columns the slots next to the first / last strip's columns
+// stored DF row: the slot of its owning strip; the left wall column is slot 0
+// of strip 0, the right wall and ghost columns follow the last strip's
+// columns, and the left ghost column is the row's last slot
 __device__ __forceinline__ int col_slot(const CaseParams& P, int x)
 {
     x = wrap_axis(x, P.nx, P.wall_x);
+    if (x < 0) return P.pitch - 1;
     const int r = min(max(floor_div(x - P.xlo, STRIP_COLS), 0), P.nstrips - 1);
-    return r * REGION_SLOTS + (x - P.xlo - r * STRIP_COLS) + 2;
+    return r * REGION_SLOTS + (x - P.xlo - r * STRIP_COLS) + 1;
 }
 
-// Calls fn(slot) for every slot that holds column x: its own slot and the
-// copies kept in neighbouring strip regions (slot 1 of the next strip, slot 62
-// of the previous one, and on a periodic axis every region slot 1..62 whose
-// column wraps onto x).
+// Calls fn(slot) for the slot that holds column x (the layout keeps one).
 template <typename F>
 __device__ __forceinline__ void for_each_slot(const CaseParams& P, int x, F&& fn)
 {
-    x = wrap_axis(x, P.nx, P.wall_x);
-    const int own = col_slot(P, x);
-    fn(own);
-    if (P.wall_x) {
-        if (x < P.xlo || x >= P.nx - 1) return;            // wall and ghost columns have no copies
-        const int r = (x - P.xlo) / STRIP_COLS, t = (x - P.xlo) % STRIP_COLS;
-        if (t == 0 && r >= 1) fn((r - 1) * REGION_SLOTS + STRIP_COLS + 2);
-        if (t == STRIP_COLS - 1 && r + 1 < P.nstrips) fn((r + 1) * REGION_SLOTS + 1);
-        return;
-    }
-    const int span_end = (P.nstrips - 1) * STRIP_COLS + STRIP_COLS;   // last column any region slot 62 holds
-    for (int d = x - P.nx; d <= span_end; d += P.nx) {
-        const int r0 = floor_div(d, STRIP_COLS);
-        for (int r = r0 - 1; r <= r0 + 1; ++r) {
-            if (r < 0 || r >= P.nstrips) continue;
-            const int j = d - r * STRIP_COLS + 2;
-            if (j < 1 || j > REGION_SLOTS - 2) continue;
-            const int slot = r * REGION_SLOTS + j;
-            if (slot != own) fn(slot);
-        }
-    }
+    fn(col_slot(P, x));
 }
 
 // Bytes of one stored row block and the byte offset of DF row q (0..17)
@@ -587,11 +565,12 @@ __device__ __forceinline__ int stored_row(int v, int n, int walled)
 }
 
 // interior item: the 64 lanes take the 64 slots of one strip region, i.e.
-// columns X - 2 .. X + 61 of a strip whose own columns are X .. X + 59, and
-// march up the rows [y0, y0 + len).  Lanes 1..62 collide valid nodes (their
-// x-neighbours are lanes 0..63); lanes 2..61 are the strip's own nodes and
-// lanes 1 and 62 refresh the copies of the neighbouring strips' edge columns,
-// so every store covers whole aligned cache lines.  All memory traffic goes
+// columns X - 1 .. X + 62 of a strip whose own columns are X .. X + 61, and
+// march up the rows [y0, y0 + len).  Lanes 1..62 collide the strip's own
+// nodes (their x-neighbours are lanes 0..63); lanes 0 and 63 only provide
+// the state of the neighbouring strips' edge columns for the gradients, and
+// on a walled x axis a lane on a wall column collides the wall node when the
+// strip takes it (XW).  All memory traffic goes
 // through buffer resources: one per stored row block, per-lane byte offsets
 // of the source slots in VGPRs, the DF row inside the block as a scalar
 // offset.  The loop body has no divergent branch: lanes whose slot must not
@@ -616,7 +595,7 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     const int xhi = wall_x ? nx - 1 : nx;          // end of the off-wall columns
     const int X = w.x0;                            // first own column
     const int region = (X - P.xlo) / STRIP_COLS * REGION_SLOTS;
-    const int c = X - 2 + lane;                    // column of this lane's slot
+    const int c = X - 1 + lane;                    // column of this lane's slot
     // the node this lane collides: its column, held inside [0, nx) on a walled axis
     const int cn = wall_x ? min(max(c, 0), nx - 1) : wrap_axis(c, nx, 0);
     const bool regular = c == cn || !wall_x;
@@ -632,12 +611,12 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
         gr3 = C(-gref::m3) * K.gsk;
         gr4 = C(-gref::m4) * K.gsk;
     }
-    // byte offset of the slot a pull along e_x reads: inside the own region
-    // for source columns X - 1 .. X + 60 (own columns and the two copies, or
-    // the wall and ghost slots on a walled side), the owning slot otherwise
+    // slot a pull along e_x reads: inside the own region for this strip's own
+    // columns, the owning slot (col_slot) for the neighbouring strips'
+    // columns and the wall, ghost and wrapped columns
     auto src_slot = [&](int ex) {
-        const int d = c - ex, p = d - (X - 2);
-        const bool inside = regular && p >= 1 && p <= REGION_SLOTS - 2 && (!wall_x || (d >= -1 && d <= nx));
+        const int d = c - ex, p = d - (X - 1);
+        const bool inside = regular && p >= 1 && p <= STRIP_COLS && d >= P.xlo && d < xhi;
         return inside ? region + p : col_slot(P, cn - ex);
     };
     const int sl0 = src_slot(1), sl1 = src_slot(0), sl2 = src_slot(-1);
@@ -649,17 +628,20 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     XWallLane xl{false, false, P.extrap_order == 2};
     if constexpr (XW) {
         xl.left = c == 0;
-        xl.wall = lane >= 1 && lane <= REGION_SLOTS - 2 && (c == 0 || c == nx - 1);
+        xl.wall = c == 0 || c == nx - 1;
     }
     // the strip holds the left / right wall column (wave-uniform)
-    const bool has_left = XW && X == P.xlo, has_right = XW && X + STRIP_COLS >= nx - 1;
-    // slots this lane stores: all but the wall and ghost slots of a walled
-    // side (unless the lane collides the wall node) and the slots past the
-    // ghost column of a ragged last strip, which nothing reads
-    const bool keep = wall_x && (c == -1 || c == 0 || c >= nx - 1) && !xl.wall;
+    const bool has_left = XW && X == P.xlo, has_right = XW && X + STRIP_COLS >= nx - 1;   // lanes 0 .. 63 reach X + 62
+    // slots this lane stores: the whole region, so that every store covers
+    // whole cache lines (a partly written line costs the memory system a
+    // read-modify-write), except the wall and ghost slots of a walled side,
+    // unless the lane collides the wall node, and the slots past the end of
+    // a ragged last strip.  The halo lanes 0 and 63 write slots that nothing
+    // reads.
+    const bool keep = !xl.wall && (wall_x ? (c < P.xlo || c >= xhi) : c > nx);
     const int vf_out = keep ? kDropOffset : (region + lane) * EF;
     const int vg_out = keep ? kDropOffset : (region + lane) * EG;
-    const bool out_lane = lane >= 2 && lane < 2 + STRIP_COLS && c < xhi;   // own nodes
+    const bool out_lane = lane >= 1 && lane <= STRIP_COLS && c >= P.xlo && c < xhi;   // own nodes
     const int frow_bytes = pitch * EF, grow_bytes = pitch * EG, g_base = 9 * frow_bytes;
     const unsigned blk_bytes = unsigned(9 * (frow_bytes + grow_bytes));
     const long long blk = blk_bytes;
@@ -681,7 +663,7 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     };
     // A strip next to an x-wall has lanes on the wall column; their state
     // takes the wall velocity / temperature by selection (no divergence).
-    const bool edge = Tuning<Fm>::edge_select && wall_x && (X - 2 <= 0 || X + REGION_SLOTS - 3 >= nx - 1);
+    const bool edge = Tuning<Fm>::edge_select && wall_x && (X - 1 <= 0 || X + STRIP_COLS >= nx - 1);
     // moments and state of a pulled row (wall rows: uniform branch to the wall formulas)
     auto row_state = [&](int yy, const C f[9], const C g[9], C dm[9], C dn[9], NodeState<C>& st) {
         to_moments<C>(f, dm);
@@ -814,7 +796,7 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
             // direction (the bounce-back of the next pull)
             const rsrc_t rp = make_rsrc(dst + (long long)stored_row(y + 1, ny, wall_y) * blk, blk_bytes);
             const rsrc_t rm = make_rsrc(dst + (long long)stored_row(y - 1, ny, wall_y) * blk, blk_bytes);
-            const int gsl = region + (xl.left ? lane - 1 : lane + 1);
+            const int gsl = col_slot(P, xl.left ? -1 : c + 1);   // the wall lane's ghost slot
             // gb is relative to the 16-bit reference of the wall column; the
             // ghost column next to it (x -/+ 1) has offsets v_q gsk higher / lower
             C gka = C(0), gkd = C(0);
