@@ -175,7 +175,8 @@ long long lbm_case_diverged_at(const lbm_ctx* ctx, int case_id);
 
 /* Launch configuration of the step: compiled kernel variant (0: the
  * hand-tuned one; 1: wave priority by progress flipped; 2: LDS parking of
- * the row ahead flipped; 3: the other block size, 4 <-> 8 wavefronts),
+ * the row ahead flipped; 3: the other block size, 4 <-> 8 wavefronts; 4:
+ * lockstep march flipped),
  * scale of the modelled cost of an edge-strip row, and row bands per XCD of
  * the work list.  The physics does not depend on it: results are bitwise
  * equal for every configuration. */
@@ -184,7 +185,7 @@ lbm_status lbm_set_launch_config(lbm_ctx* ctx, int variant, double xw_scale, int
 /* Autotuner of the launch configuration.  If cache_path names a file that
  * holds an entry for this context's key (device architecture, storage
  * format, grid and wall signature of its cases), that entry is applied and
- * no trial runs.  Otherwise every configuration (4 kernel variants x 3
+ * no trial runs.  Otherwise every configuration (5 kernel variants x 3
  * edge-cost scales when a case has x-walls x 3 band counts: 4, 1, 16 per
  * XCD) is timed over
  * trial_steps steps (0: about 2e7 node updates) from the current state,

@@ -8,7 +8,7 @@
 namespace lbm {
 
 // Tuning variants compiled per storage format (see lbm_step.hpp).
-constexpr int NUM_STEP_VARIANTS = 4;
+constexpr int NUM_STEP_VARIANTS = 5;
 
 // What the work list of a step kernel variant must follow.
 struct StepShape {

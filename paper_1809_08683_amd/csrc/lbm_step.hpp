@@ -109,8 +109,9 @@ template <> struct Tuning<FmtF16> {
 // Tuning variants of a format, for the autotuner (lbm_autotune): variant 0
 // is the hand-tuned set above; 1 flips the progress priority, 2 flips the
 // LDS parking of the ahead row, 3 takes the other block size (4 <-> 8
-// wavefronts).  Everything else, the lockstep rule included, stays that of
-// the format, so the work list built for a variant always matches it.
+// wavefronts), 4 flips the lockstep march.  Everything else stays that of
+// the format.  The host builds the work list from the variant's shape (block
+// size, lockstep, occupancy; step_shape_v), so the two always match.
 template <typename Base, int V>
 struct Variant : Base {
 };
@@ -119,8 +120,9 @@ struct Tuning<Variant<Base, V>> : Tuning<Base> {
     static constexpr bool fair = (V == 1) != Tuning<Base>::fair;
     static constexpr bool park = (V == 2) != Tuning<Base>::park;
     static constexpr int block_waves = V == 3 ? (Tuning<Base>::block_waves == 8 ? 4 : 8) : Tuning<Base>::block_waves;
+    static constexpr bool lockstep = (V == 4) != Tuning<Base>::lockstep;
 };
-static_assert(NUM_STEP_VARIANTS == 4, "variants 0-3 are defined above");
+static_assert(NUM_STEP_VARIANTS == 5, "variants 0-4 are defined above");
 
 static_assert(REGION_SLOTS == WAVE && STRIP_COLS == WAVE - 2, "one wavefront per strip region");
 
@@ -1209,6 +1211,7 @@ int with_variant(int v, Fn&& fn)
     case 1: return fn(Variant<Base, 1>{});
     case 2: return fn(Variant<Base, 2>{});
     case 3: return fn(Variant<Base, 3>{});
+    case 4: return fn(Variant<Base, 4>{});
     default: return fn(Variant<Base, 0>{});
     }
 }

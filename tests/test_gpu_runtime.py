@@ -56,13 +56,13 @@ def _same(b1, b2, n):
 def test_every_launch_configuration_gives_the_same_state(prec):
     ref, cases = _batch(prec)
     ref.step(12)
-    for variant in range(4):
+    for variant in range(5):
         for xw_scale, bands in ((1.0, 4), (0.85, 1), (1.2, 4)):
             print(f"{prec}: variant {variant} xw_scale {xw_scale} bands {bands}", flush=True)
             b, _ = _batch(prec)
             b.set_launch_config(variant, xw_scale, bands)
             b.step(5)
-            b.set_launch_config((variant + 1) % 4, 1.0, 4)   # switching mid-run keeps the state
+            b.set_launch_config((variant + 1) % 5, 1.0, 4)   # switching mid-run keeps the state
             b.step(7)
             _same(ref, b, len(cases))
             b.close()
@@ -102,7 +102,7 @@ def test_autotune_keeps_the_state_and_uses_its_cache(tmp_path):
     before = [b.macros(k) for k in range(len(cases))]
     r = b.autotune(trial_steps=5, cache_path=cache)
     print("tuned:", r, flush=True)
-    assert r["trials"] == 4 * 3 * 3 and r["from_cache"] == 0
+    assert r["trials"] == 5 * 3 * 3 and r["from_cache"] == 0
     assert r["ms_per_step"] <= r["default_ms_per_step"] * 1.0001
     assert (r["variant"], r["xw_scale"], r["bands_per_xcd"]) == (0, 1.0, 4) or \
         r["ms_per_step"] < 0.99 * r["default_ms_per_step"]
