@@ -291,16 +291,22 @@ long long  lbm_work_items(const lbm_ctx* ctx);
  * hardware byte counters. */
 lbm_status lbm_copy_bandwidth(size_t bytes, int iters, void* hip_stream, double* gbps, double* ms_per_copy);
 
-/* Stochastic rounding of the 16-bit formats, computed on the host with the
- * kernels' own code (no GPU needed; for tests and diagnostics).
- * lbm_rounding_byte: the random byte (0-255) with which DF row q (0-8 f,
- * 9-17 g) of node (x, y) is rounded when stored in step t under storage
- * precision prec; 0 for rows that the precision does not store in 16 bits,
- * for prec outside lbm_precision and for q outside 0-17.
- * lbm_round_half_stochastic: the FP16 value, returned as float, that v is
- * stored as with random byte u (u mod 256). */
-unsigned   lbm_rounding_byte(int prec, int x, int y, unsigned t, int q);
-float      lbm_round_half_stochastic(float v, unsigned u);
+/* Stochastic rounding of the 16-bit formats (diagnostics and tests).
+ * lbm_rounding_operand: the 32-bit random operand with which DF row q (0-8
+ * f, 9-17 g) of node (x, y) is rounded when stored in step t under storage
+ * precision prec, computed on the host with the kernels' code; 0 for rows
+ * that the precision does not store in 16 bits, for prec outside
+ * lbm_precision and for q outside 0-17.
+ * lbm_round_half_stochastic: the library's host model of the device's
+ * rounding (v_cvt_sr_f16_f32): the FP16 value that v (|v| < 65504) is
+ * stored as with operand r.
+ * lbm_round_half_device: the same on the device with the store codec's
+ * code, for n values; v, r and out are device pointers of n elements,
+ * hip_stream NULL for the default stream; waits for the result.  LBM_EINVAL
+ * for n < 0 or a NULL pointer with n > 0, LBM_EDEVICE on a HIP error. */
+unsigned   lbm_rounding_operand(int prec, int x, int y, unsigned t, int q);
+double     lbm_round_half_stochastic(float v, unsigned r);
+lbm_status lbm_round_half_device(const float* v, const unsigned* r, float* out, long long n, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -1,7 +1,6 @@
 // Host runtime and C ABI (include/lbm.h) of the gfx950 lattice Boltzmann
 // library: parameter validation and derived constants, device memory, the
 // per-step work list, launches, reductions and checkpoints.
-#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1394,15 +1393,21 @@ void lbm_destroy(lbm_ctx* c)
 
 }  // extern "C"
 
-unsigned lbm_rounding_byte(int prec, int x, int y, unsigned t, int q)
+unsigned lbm_rounding_operand(int prec, int x, int y, unsigned t, int q)
 {
     if (q < 0 || q > 17) return 0u;
-    if (prec == LBM_FP16S) return lbm::sr::byte_at(x, y, t, q);
-    if (prec == LBM_F32G16 && q >= 9) return lbm::sr::byte_at(x, y, t, q - 9);
+    if (prec == LBM_FP16S) return lbm::sr::operand_at(x, y, t, q);
+    if (prec == LBM_F32G16 && q >= 9) return lbm::sr::operand_at(x, y, t, q - 9);
     return 0u;
 }
 
-float lbm_round_half_stochastic(float v, unsigned u)
+double lbm_round_half_stochastic(float v, unsigned r) { return lbm::round_half_stochastic_model(v, r); }
+
+lbm_status lbm_round_half_device(const float* v, const unsigned* r, float* out, long long n, void* hip_stream)
 {
-    return __half2float(__float2half_rn(lbm::round_stochastic_half(v, u & 0xFFu)));
+    if (n < 0 || (n > 0 && (!v || !r || !out))) return LBM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int rc = lbm::launch_round_half(v, r, out, n, st);
+    if (rc != 0) return LBM_EDEVICE;
+    return hipStreamSynchronize(st) == hipSuccess ? LBM_OK : LBM_EDEVICE;
 }

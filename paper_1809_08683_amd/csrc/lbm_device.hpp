@@ -648,11 +648,21 @@ template <> struct Store<float> {
 };
 template <> struct Store<__half> {
     using C = float;
-    // stochastic rounding with the random byte u (lbm_rounding.hpp)
-    static __device__ __forceinline__ void store_sr(__half* p, float v, unsigned u) { store(p, round_stochastic_half(v, u)); }
-    static __device__ __forceinline__ void bstore_sr(rsrc_t r, int vo, int so, float v, unsigned u)
+    // stochastic rounding with the random operand rnd (v_cvt_sr_f16_f32; lbm_rounding.hpp)
+    static __device__ __forceinline__ unsigned short sr_bits(float v, unsigned rnd)
     {
-        bstore(r, vo, so, round_stochastic_half(v, u));
+        typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+        const half2_t old = {0, 0};
+        const half2_t h = __builtin_amdgcn_cvt_sr_f16_f32(old, v, rnd, false);
+        return __builtin_bit_cast(unsigned short, h[0]);
+    }
+    static __device__ __forceinline__ void store_sr(__half* p, float v, unsigned rnd)
+    {
+        *reinterpret_cast<unsigned short*>(p) = sr_bits(v, rnd);
+    }
+    static __device__ __forceinline__ void bstore_sr(rsrc_t r, int vo, int so, float v, unsigned rnd)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(sr_bits(v, rnd), r, vo, so, kStorePolicy);
     }
     static __device__ __forceinline__ float load(const __half* p)
     {

@@ -124,9 +124,26 @@ __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ sr
     if (i < n) dst[i] = src[i];
 }
 
+// FP16 stochastic rounding of n values with the store codec's own code
+// (diagnostics): out[i] = the stored FP16 value of v[i] with operand r[i].
+__global__ __launch_bounds__(256) void round_half_kernel(const float* __restrict__ v, const unsigned* __restrict__ r,
+                                                         float* __restrict__ out, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = __half2float(__ushort_as_half(Store<__half>::sr_bits(v[i], r[i])));
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
+int launch_round_half(const float* v, const unsigned* r, float* out, long long n, hipStream_t stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(round_half_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream, v, r, out, n);
+    return int(hipGetLastError());
+}
+
 int launch_copy(const void* src, void* dst, long long bytes, hipStream_t stream)
 {
     const long long n = bytes / 16;

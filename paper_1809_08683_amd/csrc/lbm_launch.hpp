@@ -29,6 +29,7 @@ int launch_totals(const CaseParams* d_cases, int case_id, double* d_partial, int
                   hipStream_t stream);
 int launch_nusselt(const CaseParams* d_cases, int case_id, int side, double* d_out, hipStream_t stream);
 int launch_copy(const void* src, void* dst, long long bytes, hipStream_t stream);
+int launch_round_half(const float* v, const unsigned* r, float* out, long long n, hipStream_t stream);
 
 #define LBM_DECLARE_FORMAT(NAME)                                                                             \
     int launch_step_##NAME(int variant, const CaseParams* d_cases, const WorkItem* d_work, int nwork,        \

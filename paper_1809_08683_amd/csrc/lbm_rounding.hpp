@@ -1,34 +1,27 @@
-// Stochastic rounding of the 16-bit storage formats: the rounding itself and
-// the counter-based random bytes it uses.  Host and device share this code
-// (the library's diagnostics call it on the host).
+// Stochastic rounding of the 16-bit storage formats: the counter-based
+// random operands and a host model of the rounding.  Host and device share
+// the random-number code (the library's diagnostics call it on the host).
 //
 // Rounding to nearest stores a slowly varying value with the same error step
 // after step; on fine grids the change of a DF per step falls below half an
 // FP16 unit in the last place, and these errors add up to a bias of the heat
 // flux that grows with the grid.  The 16-bit rows are therefore rounded
-// stochastically, with one random byte per stored value drawn from a hash of
-// the node's column and row, the step counter and the value's index among
-// the format's 16-bit rows (FP16S: f rows 0-8, g rows 9-17; FP32 f + FP16 g:
-// g rows 0-8).  The bytes depend on nothing else, so every launch
-// configuration, graph replays and the copies of a column store the same
-// bits.
+// stochastically: gfx950's v_cvt_sr_f16_f32 adds a 32-bit random operand to
+// the discarded part of the FP32 value, aligned to the operand's top bit, and
+// rounds the magnitude up on a carry, so the stored value is unbiased when
+// the operand's top bits are uniform.  The operand of a value comes from a
+// hash of its node's column and row, the step counter and the value's index
+// among the format's 16-bit rows (FP16S: f rows 0-8, g rows 9-17; FP32 f +
+// FP16 g: g rows 0-8), and from nothing else, so every launch configuration,
+// graph replays and repeated runs store the same bits.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
-namespace lbm {
+#include <algorithm>
+#include <cmath>
 
-// FP32 value rounded stochastically to the FP16 grid, u a uniform random
-// byte.  Adding (u + 1/2)/256 of an FP16 unit in the last place to the
-// magnitude and cutting the FP32 mantissa to FP16's 10 bits rounds up with
-// probability equal to the cut fraction (to 1/512), so the stored value is
-// unbiased; the result is exact in FP16 and converts without a second
-// rounding (FP16 subnormals, below 6.1e-5, round to nearest once more).
-__host__ __device__ inline float round_stochastic_half(float v, unsigned u)
-{
-    const unsigned b = __builtin_bit_cast(unsigned, v);
-    return __builtin_bit_cast(float, (b + (u << 5) + 16u) & 0xFFFFE000u);
-}
+namespace lbm {
 
 namespace sr {
 __host__ __device__ inline unsigned seed_x(int x) { return unsigned(x) * 0x9E3779B1u; }
@@ -51,19 +44,40 @@ __host__ __device__ inline unsigned xorshift(unsigned w)
     w ^= w << 5;
     return w;
 }
-// random byte i of a node with mixed seed h: byte i % 4 of word i / 4, where
-// word 0 is h and word k + 1 the xorshift32 step of word k (every byte of
-// every word is uniform)
-__host__ __device__ inline unsigned byte(unsigned h, int i)
+__host__ __device__ inline unsigned rotl(unsigned w, int s) { return s == 0 ? w : (w << s) | (w >> (32 - s)); }
+// Random operand i of a node with mixed seed h: word i / 4 rotated left by
+// 8 (i % 4) bits, where word 0 is h and word k + 1 the xorshift32 step of
+// word k.  The four operands of a word have distinct top bytes (every byte
+// of every word is uniform); their lower bits overlap, which leaves each
+// rounding unbiased.
+__host__ __device__ inline unsigned operand(unsigned h, int i)
 {
     for (int k = 0; k < (i >> 2); ++k) h = xorshift(h);
-    return (h >> (8 * (i & 3))) & 0xFFu;
+    return rotl(h, 8 * (i & 3));
 }
-// random byte i of the node (x, y) (wrapped on a periodic axis) in step t
-__host__ __device__ inline unsigned byte_at(int x, int y, unsigned t, int i)
+// random operand i of the node (x, y) (wrapped on a periodic axis) in step t
+__host__ __device__ inline unsigned operand_at(int x, int y, unsigned t, int i)
 {
-    return byte(mix(seed_x(x) ^ seed_yt(y, t)), i);
+    return operand(mix(seed_x(x) ^ seed_yt(y, t)), i);
 }
 }  // namespace sr
+
+// Host model of v_cvt_sr_f16_f32 for |v| < 65504: the magnitude is cut to
+// the FP16 grid (spacing 2^(e - 10) for 2^e <= |v|, 2^-24 below 2^-14) and
+// rounded up when the discarded fraction, scaled to 2^32, plus r reaches
+// 2^32.  Returns the FP16 value as a double.
+inline double round_half_stochastic_model(float v, unsigned r)
+{
+    const double a = std::fabs(double(v));
+    if (a == 0.0) return double(v);
+    int e;
+    (void)std::frexp(a, &e);           // a = m 2^e, m in [0.5, 1)
+    const double spacing = std::ldexp(1.0, std::max(e - 11, -24));
+    const double q = a / spacing, lo = std::floor(q);
+    const double frac32 = std::floor(std::ldexp(q - lo, 32));   // discarded bits past 32 are dropped
+    const double up = frac32 + double(r) >= 4294967296.0 ? 1.0 : 0.0;
+    const double res = (lo + up) * spacing;
+    return v < 0 ? -res : res;
+}
 
 }  // namespace lbm

@@ -184,14 +184,14 @@ template <typename Fm> __device__ __forceinline__ typename Fm::C load_df(const c
     using G = typename Fm::G;
     return q < 9 ? Store<F>::load(reinterpret_cast<const F*>(buf + off)) : Store<G>::load(reinterpret_cast<const G*>(buf + off));
 }
-// store of DF row q (0..17) with the random byte u of its stochastic rounding
+// store of DF row q (0..17) with the random operand rnd of its stochastic rounding
 template <typename Fm> __device__ __forceinline__ void store_df(char* buf, int q, long long off, typename Fm::C v,
-                                                                unsigned u)
+                                                                unsigned rnd)
 {
     using F = typename Fm::F;
     using G = typename Fm::G;
-    if (q < 9) Store<F>::store_sr(reinterpret_cast<F*>(buf + off), v, u);
-    else Store<G>::store_sr(reinterpret_cast<G*>(buf + off), v, u);
+    if (q < 9) Store<F>::store_sr(reinterpret_cast<F*>(buf + off), v, rnd);
+    else Store<G>::store_sr(reinterpret_cast<G*>(buf + off), v, rnd);
 }
 template <typename Fm> __device__ __forceinline__ long long slot_bytes(int q, int slot)
 {
@@ -232,12 +232,12 @@ namespace sr {
 template <typename Fm> constexpr bool used = Fm::EF == 2 || Fm::EG == 2;
 // index of DF row q (0..17) among the 16-bit rows of the format (negative: not 16-bit)
 template <typename Fm> constexpr int index(int q) { return Fm::EF == 2 ? q : q - 9; }
-// random byte of DF row q stored at (x, y) (wrapped on a periodic axis) in step t
-template <typename Fm> __device__ __forceinline__ unsigned byte_of(int x, int y, unsigned t, int q)
+// random operand of DF row q stored at (x, y) (wrapped on a periodic axis) in step t
+template <typename Fm> __device__ __forceinline__ unsigned operand_of(int x, int y, unsigned t, int q)
 {
     if constexpr (!used<Fm>) return 0u;
     if ((q < 9 ? Fm::EF : Fm::EG) != 2) return 0u;
-    return byte_at(x, y, t, index<Fm>(q));
+    return operand_at(x, y, t, index<Fm>(q));
 }
 }  // namespace sr
 template <typename C> __device__ __forceinline__ C gref_v(int q)
@@ -311,9 +311,9 @@ __device__ __forceinline__ void store_node(const CaseParams& P, char* dst, int x
     for_each_slot(P, x, [&](int slot) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            store_df<Fm>(dst, q, row_byte<Fm>(P, q, y) + slot_bytes<Fm>(q, slot), fb[q], sr::byte_of<Fm>(x, y, t, q));
+            store_df<Fm>(dst, q, row_byte<Fm>(P, q, y) + slot_bytes<Fm>(q, slot), fb[q], sr::operand_of<Fm>(x, y, t, q));
             store_df<Fm>(dst, 9 + q, row_byte<Fm>(P, 9 + q, y) + slot_bytes<Fm>(9 + q, slot), gs[q],
-                         sr::byte_of<Fm>(x, y, t, 9 + q));
+                         sr::operand_of<Fm>(x, y, t, 9 + q));
         }
     });
 }
@@ -332,7 +332,7 @@ __device__ __forceinline__ void store_ghosts(const CaseParams& P, char* dst, int
             const int qf = OPPq(q), qg = 9 + OPPq(q);
             const typename Fm::C gs = gb[q] - gref_offset<Fm>(P, OPPq(q), tx);
             const int kx = wrap_axis(tx, P.nx, P.wall_x), ky = wrap_axis(ty, P.ny, P.wall_y);
-            const unsigned uf = sr::byte_of<Fm>(kx, ky, t, qf), ug = sr::byte_of<Fm>(kx, ky, t, qg);
+            const unsigned uf = sr::operand_of<Fm>(kx, ky, t, qf), ug = sr::operand_of<Fm>(kx, ky, t, qg);
             for_each_slot(P, tx, [&](int slot) {
                 store_df<Fm>(dst, qf, row_byte<Fm>(P, qf, ty) + slot_bytes<Fm>(qf, slot), fb[q], uf);
                 store_df<Fm>(dst, qg, row_byte<Fm>(P, qg, ty) + slot_bytes<Fm>(qg, slot), gs, ug);
@@ -781,9 +781,9 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
                     w = sr::xorshift(w);
                     wk = i >> 2;
                 }
-                const unsigned u = (w >> (8 * (i & 3))) & 0xFFu;
-                if (j < 9) Store<F>::bstore_sr(ro, vf_out, q * frow_bytes, fb[q], u);
-                else Store<G>::bstore_sr(ro, vg_out, g_base + q * grow_bytes, gb[q], u);
+                const unsigned rnd = sr::rotl(w, 8 * (i & 3));
+                if (j < 9) Store<F>::bstore_sr(ro, vf_out, q * frow_bytes, fb[q], rnd);
+                else Store<G>::bstore_sr(ro, vg_out, g_base + q * grow_bytes, gb[q], rnd);
             }
         } else {
 #pragma unroll
@@ -812,22 +812,22 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
             if (has_left) {
                 // left wall: q = 3, 6, 7 leave as 1, 8, 5 in rows y, y + 1, y - 1
                 const int vf = xl.wall && xl.left ? gsl * EF : kDropOffset, vg = xl.wall && xl.left ? gsl * EG : kDropOffset;
-                Store<F>::bstore_sr(ro, vf, 1 * frow_bytes, fb[3], sr::byte_of<Fm>(gcol, y, tk, 1));
-                Store<G>::bstore_sr(ro, vg, g_base + 1 * grow_bytes, gb[3] + gka, sr::byte_of<Fm>(gcol, y, tk, 10));
-                Store<F>::bstore_sr(rp, vf, 8 * frow_bytes, fb[6], sr::byte_of<Fm>(gcol, yp, tk, 8));
-                Store<G>::bstore_sr(rp, vg, g_base + 8 * grow_bytes, gb[6] + gkd, sr::byte_of<Fm>(gcol, yp, tk, 17));
-                Store<F>::bstore_sr(rm, vf, 5 * frow_bytes, fb[7], sr::byte_of<Fm>(gcol, ym, tk, 5));
-                Store<G>::bstore_sr(rm, vg, g_base + 5 * grow_bytes, gb[7] + gkd, sr::byte_of<Fm>(gcol, ym, tk, 14));
+                Store<F>::bstore_sr(ro, vf, 1 * frow_bytes, fb[3], sr::operand_of<Fm>(gcol, y, tk, 1));
+                Store<G>::bstore_sr(ro, vg, g_base + 1 * grow_bytes, gb[3] + gka, sr::operand_of<Fm>(gcol, y, tk, 10));
+                Store<F>::bstore_sr(rp, vf, 8 * frow_bytes, fb[6], sr::operand_of<Fm>(gcol, yp, tk, 8));
+                Store<G>::bstore_sr(rp, vg, g_base + 8 * grow_bytes, gb[6] + gkd, sr::operand_of<Fm>(gcol, yp, tk, 17));
+                Store<F>::bstore_sr(rm, vf, 5 * frow_bytes, fb[7], sr::operand_of<Fm>(gcol, ym, tk, 5));
+                Store<G>::bstore_sr(rm, vg, g_base + 5 * grow_bytes, gb[7] + gkd, sr::operand_of<Fm>(gcol, ym, tk, 14));
             }
             if (has_right) {
                 // right wall: q = 1, 5, 8 leave as 3, 7, 6 in rows y, y + 1, y - 1
                 const int vf = xl.wall && !xl.left ? gsl * EF : kDropOffset, vg = xl.wall && !xl.left ? gsl * EG : kDropOffset;
-                Store<F>::bstore_sr(ro, vf, 3 * frow_bytes, fb[1], sr::byte_of<Fm>(gcol, y, tk, 3));
-                Store<G>::bstore_sr(ro, vg, g_base + 3 * grow_bytes, gb[1] - gka, sr::byte_of<Fm>(gcol, y, tk, 12));
-                Store<F>::bstore_sr(rp, vf, 7 * frow_bytes, fb[5], sr::byte_of<Fm>(gcol, yp, tk, 7));
-                Store<G>::bstore_sr(rp, vg, g_base + 7 * grow_bytes, gb[5] - gkd, sr::byte_of<Fm>(gcol, yp, tk, 16));
-                Store<F>::bstore_sr(rm, vf, 6 * frow_bytes, fb[8], sr::byte_of<Fm>(gcol, ym, tk, 6));
-                Store<G>::bstore_sr(rm, vg, g_base + 6 * grow_bytes, gb[8] - gkd, sr::byte_of<Fm>(gcol, ym, tk, 15));
+                Store<F>::bstore_sr(ro, vf, 3 * frow_bytes, fb[1], sr::operand_of<Fm>(gcol, y, tk, 3));
+                Store<G>::bstore_sr(ro, vg, g_base + 3 * grow_bytes, gb[1] - gka, sr::operand_of<Fm>(gcol, y, tk, 12));
+                Store<F>::bstore_sr(rp, vf, 7 * frow_bytes, fb[5], sr::operand_of<Fm>(gcol, yp, tk, 7));
+                Store<G>::bstore_sr(rp, vg, g_base + 7 * grow_bytes, gb[5] - gkd, sr::operand_of<Fm>(gcol, yp, tk, 16));
+                Store<F>::bstore_sr(rm, vf, 6 * frow_bytes, fb[8], sr::operand_of<Fm>(gcol, ym, tk, 6));
+                Store<G>::bstore_sr(rm, vg, g_base + 6 * grow_bytes, gb[8] - gkd, sr::operand_of<Fm>(gcol, ym, tk, 15));
             }
         }
         if (EXPORT && (out_lane || xl.wall)) export_node<C>(P, c, y, s_c, K.T0_d + double(s_c.dT));

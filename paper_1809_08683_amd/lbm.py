@@ -124,8 +124,9 @@ def load_library():
         "lbm_batch_nusselt": ([vp, C.c_int, _D, C.POINTER(C.c_int)], C.c_int),
         "lbm_work_items": ([vp], C.c_longlong),
         "lbm_copy_bandwidth": ([C.c_size_t, C.c_int, vp, _D, _D], C.c_int),
-        "lbm_rounding_byte": ([C.c_int, C.c_int, C.c_int, C.c_uint, C.c_int], C.c_uint),
-        "lbm_round_half_stochastic": ([C.c_float, C.c_uint], C.c_float),
+        "lbm_rounding_operand": ([C.c_int, C.c_int, C.c_int, C.c_uint, C.c_int], C.c_uint),
+        "lbm_round_half_stochastic": ([C.c_float, C.c_uint], C.c_double),
+        "lbm_round_half_device": ([vp, vp, vp, C.c_longlong, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -142,7 +143,7 @@ def exported_symbols():
             "lbm_save", "lbm_load", "lbm_time", "lbm_last_error", "lbm_destroy",
             "lbm_batch_create", "lbm_batch_size", "lbm_case_init", "lbm_case_init_static", "lbm_case_macros",
             "lbm_case_nusselt", "lbm_case_totals", "lbm_batch_flags", "lbm_batch_step", "lbm_batch_nusselt", "lbm_work_items",
-            "lbm_copy_bandwidth", "lbm_rounding_byte", "lbm_round_half_stochastic"]
+            "lbm_copy_bandwidth", "lbm_rounding_operand", "lbm_round_half_stochastic", "lbm_round_half_device"]
 
 
 def copy_bandwidth(nbytes: int, iters: int = 20, stream=None):
@@ -155,16 +156,32 @@ def copy_bandwidth(nbytes: int, iters: int = 20, stream=None):
     return g.value, ms.value
 
 
-def rounding_byte(prec, x: int, y: int, t: int, q: int) -> int:
-    """Random byte (0-255) of the stochastic rounding of DF row q at node
+def rounding_operand(prec, x: int, y: int, t: int, q: int) -> int:
+    """32-bit random operand of the stochastic rounding of DF row q at node
     (x, y) in step t (host computation with the kernels' code)."""
-    return int(load_library().lbm_rounding_byte(PREC[prec] if isinstance(prec, str) else int(prec),
-                                                 int(x), int(y), int(t) & 0xFFFFFFFF, int(q)))
+    return int(load_library().lbm_rounding_operand(PREC[prec] if isinstance(prec, str) else int(prec),
+                                                    int(x), int(y), int(t) & 0xFFFFFFFF, int(q)))
 
 
-def round_half_stochastic(v: float, u: int) -> float:
-    """The FP16 value (as float) that v is stored as with random byte u."""
-    return float(load_library().lbm_round_half_stochastic(float(v), int(u)))
+def round_half_stochastic(v: float, r: int) -> float:
+    """The library's host model of the device's stochastic FP16 rounding."""
+    return float(load_library().lbm_round_half_stochastic(float(v), int(r) & 0xFFFFFFFF))
+
+
+def round_half_device(v, r, stream=None):
+    """Stochastic FP16 rounding on the device with the store codec's code:
+    v (float32) and r (int32 bit patterns) are device tensors of equal
+    length; returns the FP16 values as a float32 device tensor."""
+    import torch
+    if v.dtype != torch.float32 or r.dtype != torch.int32 or v.numel() != r.numel():
+        raise ValueError("v must be float32 and r int32 of the same length")
+    v, r = v.contiguous(), r.contiguous()
+    out = torch.empty_like(v)
+    rc = load_library().lbm_round_half_device(v.data_ptr(), r.data_ptr(), out.data_ptr(), v.numel(),
+                                              _stream_handle(stream))
+    if rc != OK:
+        raise LBMError(rc, "lbm_round_half_device")
+    return out
 
 
 def _ptr(a):
