@@ -239,6 +239,31 @@ def batch_accuracy(steps, prec="f32"):
     }
 
 
+def format_accuracy(precs, cases=((256, 1e5, 100000), (1024, 1e6, 50000))):
+    """Mean hot-wall Nusselt number of each storage format against the FP64
+    path on the same cavity (eps = 0.6, tau0 = 0.8, seeded noise) after the
+    same number of steps: the 256^2 Ra = 1e5 cavity near steady state and the
+    1024^2 Ra = 1e6 cavity during its transient."""
+    from paper_1809_08683_amd import inputs, lbm
+
+    out = {}
+    for N, Ra, steps in cases:
+        nu = {}
+        for prec in ["f64"] + [p for p in precs if p != "f64"]:
+            c = inputs.cavity(N=N, Ra=Ra, eps=0.6, prec=prec, noise_seed=1)
+            g = lbm.Context(c).init(**c["init"])
+            g.step_ex(steps, allow_diverged=True)
+            nu[prec] = None if g.diverged else g.nusselt(0)
+            g.close()
+        key = f"{N}x{N} Ra {Ra:.0e}, {steps} steps"
+        out[key] = {"Nu_f64": round(nu["f64"], 6)}
+        for prec, v in nu.items():
+            if prec != "f64":
+                out[key][f"Nu_rel_err_{prec}"] = None if v is None else float(f"{(v - nu['f64']) / nu['f64']:.3g}")
+        log(f"bench: accuracy {key}: {json.dumps(out[key])}")
+    return out
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -293,6 +318,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-acc-steps", type=int, default=20000,
                     help="steps of the per-case FP32-vs-FP64 Nusselt comparison of the batched sweep (0: skip)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the per-format Nusselt comparison with the FP64 path")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: runs on one GPU only (a multi-GPU slab decomposition is designed "
@@ -321,6 +348,9 @@ def main():
         if args.batch_acc_steps > 0:
             batch["accuracy"] = batch_accuracy(args.batch_acc_steps)
             log(f"bench: batch accuracy: {json.dumps(batch['accuracy'])}")
+    accuracy = None
+    if not args.no_accuracy and "f64" in paths:
+        accuracy = format_accuracy(list(paths))
     copy_gbs, _ = lbm.copy_bandwidth(1 << 30, iters=20)
     log(f"bench: device copy bandwidth {copy_gbs:.0f} GB/s")
 
@@ -358,6 +388,8 @@ def main():
                   for k, v in paths.items()},
         "copy_bandwidth_GBs": round(copy_gbs, 1),
     }
+    if accuracy is not None:
+        out["format_accuracy"] = accuracy
     if batch is not None:
         out["batch"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in batch.items()}
     if "f64" in paths:
