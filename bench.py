@@ -146,17 +146,17 @@ def time_batch(steps, warmup, prec="f32"):
         for k, c in enumerate(cases):
             b.init(k, rho=1.0 + 1e-6 * inputs.noise(3 + k, c["nx"] * c["ny"]).reshape(c["ny"], c["nx"]))
 
-    def run(graph):
+    def run(graph, persistent=False):
         start()
         if warmup:
             b.step(warmup, allow_diverged=True)
-        if graph:                       # capture the graph of `steps` launches outside the timed region
-            b.step_ex(steps, graph=True, allow_diverged=True)
+        if graph:                       # capture the graph of `steps` steps outside the timed region
+            b.step_ex(steps, graph=True, allow_diverged=True, persistent=persistent)
             start()
             b.step(warmup, allow_diverged=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ms = b.step_ex(steps, graph=graph, allow_diverged=True)
+        ms = b.step_ex(steps, graph=graph, allow_diverged=True, persistent=persistent)
         torch.cuda.synchronize()
         return ms, time.perf_counter() - t0
 
@@ -166,6 +166,17 @@ def time_batch(steps, warmup, prec="f32"):
     log(f"bench: batch launch configuration {tune}")
     kernel_ms, wall_s = run(True)
     flags = b.flags()
+    # the same steps in one persistent launch (per-case step barriers), replayed as a graph
+    persistent = None
+    try:
+        p_ms, p_wall = run(True, persistent=True)
+        persistent = {"mlups": nodes * steps / p_wall / 1e6,
+                      "kernel_mlups": nodes / (p_ms * 1e-3 / steps) / 1e6,
+                      "frac_hbm": BYTES_PER_NODE[prec] * nodes / (p_ms * 1e-3 / steps) / 1e9 / PEAK_HBM_GBS,
+                      "stepping": "one persistent launch with per-case step barriers, replayed as a captured graph"}
+    except lbm.LBMError as e:
+        persistent = {"skipped": str(e)}
+    log(f"bench: batch persistent {persistent}")
     per_step_s = kernel_ms * 1e-3 / steps
     res = {
         "workload": "64 cavities, N in {128,256,512,1024} (seed 2), Ra log-uniform in [1e3,1e8], "
@@ -184,6 +195,7 @@ def time_batch(steps, warmup, prec="f32"):
                            "kernel_mlups": nodes / (default_ms * 1e-3 / steps) / 1e6,
                            "frac_hbm": BYTES_PER_NODE[prec] * nodes / (default_ms * 1e-3 / steps) / 1e9 / PEAK_HBM_GBS,
                            "stepping": "default configuration, one launch per step"},
+        "persistent": persistent,
     }
     res["frac_hbm"] = res["achieved_GBs"] / PEAK_HBM_GBS
     b.close()

@@ -159,14 +159,31 @@ lbm_status lbm_step(lbm_ctx* ctx, long long n);
  * with HIP events on the context stream (milliseconds). */
 lbm_status lbm_step_timed(lbm_ctx* ctx, long long n, double* ms);
 
-/* As lbm_step, with options: flags = LBM_STEP_GRAPH captures the n launches
- * into a HIP graph on first use (one graph per n and start buffer, kept
- * until the launch configuration changes or the context is destroyed) and
- * replays it, which removes the per-launch host overhead; ms != NULL
- * receives the device time of the n steps (HIP events on the context
- * stream).  Results are bitwise those of lbm_step. */
+/* As lbm_step, with options (flags, or-ed):
+ *   LBM_STEP_GRAPH captures the n steps into a HIP graph on first use (one
+ *     graph per n, start buffer and kind, kept until the launch
+ *     configuration changes or the context is destroyed) and replays it,
+ *     which removes the per-launch host overhead;
+ *   LBM_STEP_PERSISTENT runs the n steps in one launch of a persistent
+ *     kernel: every wavefront keeps its work item, and a per-case step
+ *     barrier (device-scope counters) replaces the launch boundary, so the
+ *     cases of a batch advance independently.  It needs every block of the
+ *     launch resident at once (LBM_EINVAL otherwise, with the reason in
+ *     lbm_last_error); each barrier wait gives up after a bounded number of
+ *     polls (lbm_set_persistent_spin_limit), and then the call returns
+ *     LBM_EDEVICE and every case must be initialised or loaded again.
+ *     With LBM_STEP_GRAPH the counter reset and the persistent launch are
+ *     captured together.
+ * ms != NULL receives the device time of the n steps (HIP events on the
+ * context stream).  Results are bitwise those of lbm_step. */
 #define LBM_STEP_GRAPH 1
+#define LBM_STEP_PERSISTENT 2
 lbm_status lbm_step_ex(lbm_ctx* ctx, long long n, int flags, double* ms);
+
+/* Polls of a persistent step barrier before it gives up (default 2^24,
+ * about a second; each poll sleeps about 128 cycles).  For callers that
+ * bound the time a stalled launch may take, and for tests of that path. */
+lbm_status lbm_set_persistent_spin_limit(lbm_ctx* ctx, unsigned polls);
 
 /* Time level t at the end of the step call that first found case case_id
  * diverged (the flag is checked once per call, so the divergence happened

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -84,9 +85,19 @@ struct lbm_ctx {
     int variant = 0;
     double xw_scale = 1.0;
     int bands_per_xcd = 4;
-    // instantiated graphs of n steps, by (n, start parity); dropped when the
-    // launch configuration changes
-    std::map<std::pair<long long, int>, hipGraphExec_t> graphs;
+    // instantiated graphs of n steps, by (n, start parity, persistent);
+    // dropped when the launch configuration changes
+    std::map<std::tuple<long long, int, int>, hipGraphExec_t> graphs;
+    // persistent stepping (lbm_step_ex with LBM_STEP_PERSISTENT): per-case
+    // arrival counters, the abort word and per-case wavefront counts, set up
+    // with the work list; the launch is allowed only if its blocks are all
+    // resident at once
+    unsigned* d_pcount = nullptr;
+    int* d_pabort = nullptr;
+    int* d_case_waves = nullptr;
+    bool persistent_ok = false;
+    std::string persistent_why;
+    unsigned spin_limit = 1u << 24;      // polls of a persistent step barrier before it gives up
     long long n_items = 0;               // non-empty entries
     double* d_red = nullptr;
     std::vector<void*> allocs;
@@ -509,7 +520,35 @@ lbm_status configure(lbm_ctx* c, int variant, double xw_scale, int bands_per_xcd
     }
     HIP_TRY(c, hipMemcpyAsync(c->d_work, c->work.data(), sizeof(lbm::WorkItem) * c->work.size(),
                               hipMemcpyHostToDevice, c->stream));
+    // persistent stepping: wavefronts per case, and whether all blocks of
+    // the persistent kernel are resident at once
+    const int nc = int(c->P.size());
+    std::vector<int> waves(size_t(nc), 0);
+    for (const auto& w : c->work)
+        if (w.kind != 2) ++waves[size_t(w.case_id)];
+    if (!c->d_case_waves) {
+        void* p1 = nullptr;
+        void* p2 = nullptr;
+        void* p3 = nullptr;
+        if (hipMalloc(&p1, sizeof(int) * size_t(nc)) != hipSuccess || hipMalloc(&p2, sizeof(unsigned) * size_t(nc)) != hipSuccess ||
+            hipMalloc(&p3, 256) != hipSuccess) {
+            if (p1) (void)hipFree(p1);
+            if (p2) (void)hipFree(p2);
+            return fail(c, LBM_ENOMEM, "hipMalloc of the persistent-step words failed");
+        }
+        c->d_case_waves = static_cast<int*>(p1);
+        c->d_pcount = static_cast<unsigned*>(p2);
+        c->d_pabort = static_cast<int*>(p3);
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_case_waves, waves.data(), sizeof(int) * size_t(nc), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int pbpc = 0;
+    const int pe = lbm::persistent_blocks(c->prec, variant, &pbpc);
+    const long long blocks = (long long)(c->work.size() / size_t(std::max(sh.block_waves, 1)));
+    c->persistent_ok = pe == 0 && blocks <= (long long)pbpc * cus;
+    c->persistent_why = pe != 0 ? std::string("persistent kernel occupancy query failed")
+                                : "the work list needs " + std::to_string(blocks) + " blocks, more than the " +
+                                      std::to_string((long long)pbpc * cus) + " the persistent kernel keeps resident";
     drop_graphs(c);
     c->variant = variant;
     c->xw_scale = xw_scale;
@@ -637,6 +676,18 @@ CkptCase ckpt_case(const lbm_ctx* c, size_t k)
 // context's step count after the init (a single case restarts at t = 0).
 unsigned init_tick(const lbm_ctx* c) { return unsigned(c->P.size() == 1 ? 0 : c->t); }
 
+// Enqueues n steps in one persistent launch from buffer `parity`: a kernel
+// that clears the arrival counters and the abort word, then the persistent
+// kernel (no host waits; no memset, so the pair can be captured).
+int enqueue_persistent(lbm_ctx* c, long long n, int parity)
+{
+    int rc = lbm::launch_persistent_reset(c->d_pcount, int(c->P.size()), c->d_pabort, c->stream);
+    if (rc != 0) return rc;
+    const lbm::PersistentSync sync{c->d_pcount, c->d_pabort, c->d_case_waves, c->spin_limit};
+    return lbm::launch_persistent(c->prec, c->variant, c->d_P, c->d_work, int(c->work.size()), parity, int(n), sync,
+                                  c->stream);
+}
+
 // Enqueues n step launches starting from buffer `parity` (no host waits).
 int enqueue_steps(lbm_ctx* c, long long n, int parity)
 {
@@ -652,16 +703,16 @@ int enqueue_steps(lbm_ctx* c, long long n, int parity)
 // The graph of n steps from start parity p: captured from the launch
 // sequence on first use, then reused (the kernel arguments depend only on
 // n, p and the launch configuration).
-lbm_status step_graph(lbm_ctx* c, long long n, hipGraphExec_t* out)
+lbm_status step_graph(lbm_ctx* c, long long n, bool persistent, hipGraphExec_t* out)
 {
-    const auto key = std::make_pair(n, c->parity);
+    const auto key = std::make_tuple(n, c->parity, persistent ? 1 : 0);
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
         *out = it->second;
         return LBM_OK;
     }
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    const int rc = enqueue_steps(c, n, c->parity);
+    const int rc = persistent ? enqueue_persistent(c, n, c->parity) : enqueue_steps(c, n, c->parity);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (rc != 0 || e != hipSuccess) {
@@ -677,22 +728,35 @@ lbm_status step_graph(lbm_ctx* c, long long n, hipGraphExec_t* out)
     return LBM_OK;
 }
 
-lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t e0, hipEvent_t e1, bool graph = false)
+lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t e0, hipEvent_t e1, bool graph = false,
+                     bool persistent = false)
 {
     for (size_t k = 0; k < c->H.size(); ++k)
         if (!c->H[k].inited) return fail(c, LBM_ESTATE, "lbm_step before lbm_init of every case");
     if (n < 0) return fail(c, LBM_EINVAL, "negative step count");
+    if (persistent && !c->persistent_ok) return fail(c, LBM_EINVAL, "persistent stepping: " + c->persistent_why);
+    if (persistent && n > 0x7fffffffLL) return fail(c, LBM_EINVAL, "persistent stepping: too many steps in one call");
     hipGraphExec_t exec = nullptr;
     if (graph && n > 0) {
-        lbm_status st = step_graph(c, n, &exec);
+        lbm_status st = step_graph(c, n, persistent, &exec);
         if (st != LBM_OK) return st;
     }
     if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
     if (exec) {
         HIP_TRY(c, hipGraphLaunch(exec, c->stream));
-    } else {
-        const int rc = enqueue_steps(c, n, c->parity);
+    } else if (n > 0) {
+        const int rc = persistent ? enqueue_persistent(c, n, c->parity) : enqueue_steps(c, n, c->parity);
         if (rc != 0) return hip_fail(c, hipError_t(rc), "step launch");
+    }
+    if (persistent && n > 0) {
+        int aborted = 0;
+        HIP_TRY(c, hipMemcpyAsync(&aborted, c->d_pabort, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (aborted) {
+            for (auto& h : c->H) h.inited = false;
+            return fail(c, LBM_EDEVICE, "persistent stepping: a step barrier wait gave up (spin limit); the state is "
+                                        "incomplete and every case must be initialised or loaded again");
+        }
     }
     c->parity ^= int(n & 1);
     if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
@@ -1015,13 +1079,13 @@ lbm_status lbm_step_ex(lbm_ctx* c, long long n, int flags, double* ms)
 {
     lbm_status st = check_ctx(c);
     if (st != LBM_OK) return st;
-    if (flags & ~LBM_STEP_GRAPH) return fail(c, LBM_EINVAL, "unknown step flags");
+    if (flags & ~(LBM_STEP_GRAPH | LBM_STEP_PERSISTENT)) return fail(c, LBM_EINVAL, "unknown step flags");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ms) {
         HIP_TRY(c, hipEventCreate(&e0));
         HIP_TRY(c, hipEventCreate(&e1));
     }
-    st = run_steps(c, n, e0, e1, (flags & LBM_STEP_GRAPH) != 0);
+    st = run_steps(c, n, e0, e1, (flags & LBM_STEP_GRAPH) != 0, (flags & LBM_STEP_PERSISTENT) != 0);
     if (ms && (st == LBM_OK || st == LBM_EDIVERGED)) {
         float f = 0.f;
         if (hipEventElapsedTime(&f, e0, e1) == hipSuccess) *ms = f;
@@ -1029,6 +1093,15 @@ lbm_status lbm_step_ex(lbm_ctx* c, long long n, int flags, double* ms)
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     return st;
+}
+
+lbm_status lbm_set_persistent_spin_limit(lbm_ctx* c, unsigned polls)
+{
+    lbm_status st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    c->spin_limit = polls;
+    drop_graphs(c);
+    return LBM_OK;
 }
 
 long long lbm_case_diverged_at(const lbm_ctx* c, int k)
@@ -1386,6 +1459,9 @@ void lbm_destroy(lbm_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
     if (c->d_work) (void)hipFree(c->d_work);
+    if (c->d_case_waves) (void)hipFree(c->d_case_waves);
+    if (c->d_pcount) (void)hipFree(c->d_pcount);
+    if (c->d_pabort) (void)hipFree(c->d_pabort);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;

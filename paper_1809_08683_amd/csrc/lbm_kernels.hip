@@ -134,9 +134,45 @@ __global__ __launch_bounds__(256) void round_half_kernel(const float* __restrict
     out[i] = __half2float(__ushort_as_half(Store<__half>::sr_bits(v[i], r[i])));
 }
 
+// clears the step counters and the abort word of a persistent launch
+__global__ __launch_bounds__(256) void persistent_reset_kernel(unsigned* counter, int ncases, int* abort)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ncases) counter[i] = 0u;
+    if (i == 0) *abort = 0;
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
+int launch_persistent_reset(unsigned* counter, int ncases, int* abort, hipStream_t stream)
+{
+    hipLaunchKernelGGL(persistent_reset_kernel, dim3(unsigned((std::max(ncases, 1) + 255) / 256)), dim3(256), 0,
+                       stream, counter, ncases, abort);
+    return int(hipGetLastError());
+}
+
+int launch_persistent(int prec, int variant, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
+                      int nsteps, const PersistentSync& sync, hipStream_t stream)
+{
+    switch (prec) {
+    case PREC_F64: return launch_persistent_f64(variant, d_cases, d_work, nwork, parity, nsteps, sync, stream);
+    case PREC_F32: return launch_persistent_f32(variant, d_cases, d_work, nwork, parity, nsteps, sync, stream);
+    case PREC_F32G16: return launch_persistent_f32g16(variant, d_cases, d_work, nwork, parity, nsteps, sync, stream);
+    default: return launch_persistent_f16(variant, d_cases, d_work, nwork, parity, nsteps, sync, stream);
+    }
+}
+
+int persistent_blocks(int prec, int variant, int* blocks_per_cu)
+{
+    switch (prec) {
+    case PREC_F64: return persistent_blocks_f64(variant, blocks_per_cu);
+    case PREC_F32: return persistent_blocks_f32(variant, blocks_per_cu);
+    case PREC_F32G16: return persistent_blocks_f32g16(variant, blocks_per_cu);
+    default: return persistent_blocks_f16(variant, blocks_per_cu);
+    }
+}
+
 int launch_round_half(const float* v, const unsigned* r, float* out, long long n, hipStream_t stream)
 {
     if (n <= 0) return 0;

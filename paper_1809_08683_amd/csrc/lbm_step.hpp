@@ -1026,42 +1026,17 @@ __device__ __forceinline__ void wall_item(const CaseParams& P, const WorkItem w,
 // kind 2 marks an empty slot.
 // ---------------------------------------------------------------------------
 
-// EXPORT: also write the macros of the new time level and the divergence
-// flag (the last step of a call).
+// One wavefront's share of one step: work item w of case P, from buffer
+// `parity` into the other one; tk is the step counter of the stochastic
+// rounding.  EXPORT: also write the macros of the new time level and the
+// divergence flag (the last step of a call).
 template <typename Fm, bool EXPORT>
-__global__ __launch_bounds__(WAVE * Tuning<Fm>::block_waves)
-__attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
-    const CaseParams* __restrict__ cases, const WorkItem* __restrict__ work, int nwork, int parity)
+__device__ __forceinline__ void step_item(const CaseParams& P, const WorkItem& w, int parity, unsigned tk,
+                                          typename Fm::C* park)
 {
-    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * Tuning<Fm>::block_waves + (threadIdx.x >> 6));
-    if (wid >= nwork) return;
-    // the case table and the work list are read-only during a step: reading
-    // them through the constant address space keeps them in scalar loads and
-    // registers, independent of the vector memory traffic of the DFs
-    const __attribute__((address_space(4))) WorkItem* wk = (const __attribute__((address_space(4))) WorkItem*)work + wid;
-    WorkItem w;
-    w.case_id = wk->case_id;
-    w.kind = wk->kind;
-    w.x0 = wk->x0;
-    w.y0 = wk->y0;
-    w.len = wk->len;
-    w.dir = wk->dir;
-    if (w.kind == 2) return;
-    progress_priority<Fm>(0, 1);
-    const CaseParams& P = *(const CaseParams*)(((const __attribute__((address_space(4))) CaseParams*)cases) + w.case_id);
-    // step counter of the stochastic rounding: every wavefront of the case
-    // reads this step's value and writes the next step's (the same value)
-    unsigned tk = 0u;
-    if constexpr (sr::used<Fm>) {
-        tk = __builtin_amdgcn_readfirstlane(*as_global<unsigned>(P.tick + parity));
-        if ((threadIdx.x & (WAVE - 1)) == 0) *as_global_mut<unsigned>(P.tick + (parity ^ 1)) = tk + 1u;
-    }
     if (w.kind == 0) {
         const char* src = static_cast<const char*>(P.buf[parity]);
         char* dst = static_cast<char*>(P.buf[parity ^ 1]);
-        using C = typename Fm::C;
-        __shared__ C park_lds[Tuning<Fm>::park ? Tuning<Fm>::block_waves * 18 * WAVE : 1];
-        C* park = park_lds + (Tuning<Fm>::park ? (threadIdx.x >> 6) * 18 * WAVE : 0);
         bool xw = false;
         if constexpr (Tuning<Fm>::xw_strips) xw = P.wall_x && (w.x0 == P.xlo || w.x0 + STRIP_COLS >= P.nx - 1);
         if constexpr (Tuning<Fm>::xw_strips) {
@@ -1074,6 +1049,143 @@ __attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
     }
     else
         wall_item<Fm, EXPORT>(P, w, static_cast<const char*>(P.buf[parity]), static_cast<char*>(P.buf[parity ^ 1]), tk);
+}
+
+// work item `wid` of the list, through the constant address space: the case
+// table and the work list are read-only during a launch, so they stay in
+// scalar loads and registers, independent of the vector memory traffic of
+// the DFs
+__device__ __forceinline__ WorkItem load_item(const WorkItem* work, int wid)
+{
+    const __attribute__((address_space(4))) WorkItem* wk = (const __attribute__((address_space(4))) WorkItem*)work + wid;
+    WorkItem w;
+    w.case_id = wk->case_id;
+    w.kind = wk->kind;
+    w.x0 = wk->x0;
+    w.y0 = wk->y0;
+    w.len = wk->len;
+    w.dir = wk->dir;
+    return w;
+}
+__device__ __forceinline__ const CaseParams& case_of(const CaseParams* cases, int k)
+{
+    return *(const CaseParams*)(((const __attribute__((address_space(4))) CaseParams*)cases) + k);
+}
+
+template <typename Fm, bool EXPORT>
+__global__ __launch_bounds__(WAVE * Tuning<Fm>::block_waves)
+__attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
+    const CaseParams* __restrict__ cases, const WorkItem* __restrict__ work, int nwork, int parity)
+{
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * Tuning<Fm>::block_waves + (threadIdx.x >> 6));
+    if (wid >= nwork) return;
+    const WorkItem w = load_item(work, wid);
+    if (w.kind == 2) return;
+    progress_priority<Fm>(0, 1);
+    const CaseParams& P = case_of(cases, w.case_id);
+    // step counter of the stochastic rounding: every wavefront of the case
+    // reads this step's value and writes the next step's (the same value)
+    unsigned tk = 0u;
+    if constexpr (sr::used<Fm>) {
+        tk = __builtin_amdgcn_readfirstlane(*as_global<unsigned>(P.tick + parity));
+        if ((threadIdx.x & (WAVE - 1)) == 0) *as_global_mut<unsigned>(P.tick + (parity ^ 1)) = tk + 1u;
+    }
+    using C = typename Fm::C;
+    __shared__ C park_lds[Tuning<Fm>::park ? Tuning<Fm>::block_waves * 18 * WAVE : 1];
+    C* park = park_lds + (Tuning<Fm>::park ? (threadIdx.x >> 6) * 18 * WAVE : 0);
+    step_item<Fm, EXPORT>(P, w, parity, tk, park);
+}
+
+// ---------------------------------------------------------------------------
+// persistent kernel: n steps in one launch.  Every wavefront keeps its work
+// item for all n steps; between two steps it waits until all wavefronts of
+// its case have finished the step (a per-case counter, incremented with
+// release and polled with acquire semantics at device scope), so the cases
+// of a batch advance independently and no launch boundary separates the
+// steps.  The host launches it only if every block is resident at once
+// (checked against the kernel's occupancy), so every awaited wavefront runs;
+// every wait is bounded all the same: after `spin_limit` polls the
+// wavefront raises the abort word and all wavefronts leave, so the kernel
+// always ends.  In lockstep formats the waves of a block meet at a barrier
+// per row; a wavefront whose item is shorter than the longest one of its
+// block executes the missing barriers at the end of each step, so the
+// waves of a block meet the same number of barriers per step and none waits
+// on a wave that is already waiting at its case barrier.
+// ---------------------------------------------------------------------------
+
+
+// Arrive at the end of a step and wait for the case's other wavefronts;
+// false if the wait was abandoned.
+__device__ __forceinline__ bool case_barrier(const PersistentSync& S, int case_id, unsigned target)
+{
+    int ok = 1;
+    // every lane's stores of the step, released before the arrival
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        unsigned* cnt = S.counter + case_id;
+        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned polls = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(S.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                ok = 0;
+                break;
+            }
+            if (++polls > S.spin_limit) {
+                __hip_atomic_store(S.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    // lane 0's outcome for the whole wavefront, and the acquire for its loads
+    ok = __builtin_amdgcn_readfirstlane(ok);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok != 0;
+}
+
+template <typename Fm>
+__global__ __launch_bounds__(WAVE * Tuning<Fm>::block_waves)
+__attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void persistent_kernel(
+    const CaseParams* __restrict__ cases, const WorkItem* __restrict__ work, int nwork, int parity, int nsteps,
+    PersistentSync S)
+{
+    constexpr int PB = Tuning<Fm>::block_waves;
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * PB + (threadIdx.x >> 6));
+    if (wid >= nwork) return;
+    const WorkItem w = load_item(work, wid);
+    if (w.kind == 2) return;
+    // row barriers per step of the block's longest interior item
+    int rows_max = 0;
+    if constexpr (Tuning<Fm>::lockstep) {
+        const int first = wid - (threadIdx.x >> 6);
+        for (int k = 0; k < PB && first + k < nwork; ++k) {
+            const WorkItem o = load_item(work, first + k);
+            if (o.kind == 0) rows_max = max(rows_max, o.len);
+        }
+    }
+    const CaseParams& P = case_of(cases, w.case_id);
+    unsigned tk0 = 0u;
+    if constexpr (sr::used<Fm>) tk0 = __builtin_amdgcn_readfirstlane(*as_global<unsigned>(P.tick + parity));
+    const unsigned waves = unsigned(S.case_waves[w.case_id]);
+    using C = typename Fm::C;
+    __shared__ C park_lds[Tuning<Fm>::park ? PB * 18 * WAVE : 1];
+    C* park = park_lds + (Tuning<Fm>::park ? (threadIdx.x >> 6) * 18 * WAVE : 0);
+    for (int s = 0; s < nsteps; ++s) {
+        const int par = (parity + s) & 1;
+        const unsigned tk = tk0 + unsigned(s);
+        progress_priority<Fm>(0, 1);
+        if constexpr (sr::used<Fm>) {
+            if ((threadIdx.x & (WAVE - 1)) == 0) *as_global_mut<unsigned>(P.tick + (par ^ 1)) = tk + 1u;
+        }
+        if (s + 1 < nsteps) step_item<Fm, false>(P, w, par, tk, park);
+        else step_item<Fm, true>(P, w, par, tk, park);
+        if constexpr (Tuning<Fm>::lockstep) {
+            const int own = w.kind == 0 ? w.len : 0;
+            for (int i = own; i < rows_max; ++i) __syncthreads();
+        }
+        if (s + 1 < nsteps && !case_barrier(S, w.case_id, waves * unsigned(s + 1))) return;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1190,6 +1302,26 @@ int launch_step_v(const CaseParams* d_cases, const WorkItem* d_work, int nwork, 
 }
 
 template <typename Fm>
+int launch_persistent_v(const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity, int nsteps,
+                        const PersistentSync& sync, hipStream_t stream)
+{
+    constexpr int pb = Tuning<Fm>::block_waves;
+    const dim3 block(WAVE * pb);
+    const dim3 grid((nwork + pb - 1) / pb);
+    hipLaunchKernelGGL((persistent_kernel<Fm>), grid, block, 0, stream, d_cases, d_work, nwork, parity, nsteps, sync);
+    return int(hipGetLastError());
+}
+
+// resident blocks per CU of the persistent kernel
+template <typename Fm>
+int persistent_blocks_v(int* blocks_per_cu)
+{
+    *blocks_per_cu = 0;
+    return int(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, persistent_kernel<Fm>,
+                                                            WAVE * Tuning<Fm>::block_waves, 0));
+}
+
+template <typename Fm>
 int step_shape_v(StepShape* out)
 {
     out->lockstep = Tuning<Fm>::lockstep ? 1 : 0;
@@ -1233,6 +1365,22 @@ int step_shape_fmt(int variant, StepShape* out)
 }
 
 template <typename Base>
+int launch_persistent_fmt(int variant, const CaseParams* d_cases, const WorkItem* d_work, int nwork, int parity,
+                          int nsteps, const PersistentSync& sync, hipStream_t stream)
+{
+    if (nwork == 0 || nsteps <= 0) return 0;
+    return with_variant<Base>(variant, [&](auto fm) {
+        return launch_persistent_v<decltype(fm)>(d_cases, d_work, nwork, parity, nsteps, sync, stream);
+    });
+}
+
+template <typename Base>
+int persistent_blocks_fmt(int variant, int* blocks_per_cu)
+{
+    return with_variant<Base>(variant, [&](auto fm) { return persistent_blocks_v<decltype(fm)>(blocks_per_cu); });
+}
+
+template <typename Base>
 int launch_init_fmt(const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields, int parity,
                     unsigned t0, hipStream_t stream)
 {
@@ -1249,6 +1397,15 @@ int launch_init_fmt(const CaseParams* d_cases, int case_id, long long nodes, con
         return launch_step_fmt<FMT>(variant, d_cases, d_work, nwork, parity, export_macros, stream);         \
     }                                                                                                        \
     int step_shape_##NAME(int variant, StepShape* out) { return step_shape_fmt<FMT>(variant, out); }         \
+    int launch_persistent_##NAME(int variant, const CaseParams* d_cases, const WorkItem* d_work, int nwork,  \
+                                 int parity, int nsteps, const PersistentSync& sync, hipStream_t stream)     \
+    {                                                                                                        \
+        return launch_persistent_fmt<FMT>(variant, d_cases, d_work, nwork, parity, nsteps, sync, stream);    \
+    }                                                                                                        \
+    int persistent_blocks_##NAME(int variant, int* blocks_per_cu)                                            \
+    {                                                                                                        \
+        return persistent_blocks_fmt<FMT>(variant, blocks_per_cu);                                           \
+    }                                                                                                        \
     int launch_init_##NAME(const CaseParams* d_cases, int case_id, long long nodes, const double* d_fields,  \
                            int parity, unsigned t0, hipStream_t stream)                                      \
     {                                                                                                        \

@@ -67,6 +67,7 @@ class TuneResult(C.Structure):
 
 
 STEP_GRAPH = 1
+STEP_PERSISTENT = 2
 TUNE_CACHE = os.path.join(_HERE, "tune_cache.json")
 
 _lib = None
@@ -101,6 +102,7 @@ def load_library():
         "lbm_step_ex": ([vp, C.c_longlong, C.c_int, _D], C.c_int),
         "lbm_case_diverged_at": ([vp, C.c_int], C.c_longlong),
         "lbm_set_launch_config": ([vp, C.c_int, C.c_double, C.c_int], C.c_int),
+        "lbm_set_persistent_spin_limit": ([vp, C.c_uint], C.c_int),
         "lbm_autotune": ([vp, C.c_int, C.c_char_p, C.POINTER(TuneResult)], C.c_int),
         "lbm_macros": ([vp, _D, _D, _D, _D, _D], C.c_int),
         "lbm_nusselt": ([vp, C.c_int, _D], C.c_int),
@@ -139,7 +141,8 @@ def load_library():
 def exported_symbols():
     """Names of the C ABI entry points this binding calls."""
     return ["lbm_create", "lbm_workspace_bytes", "lbm_create_ex", "lbm_init", "lbm_step",
-            "lbm_step_timed", "lbm_step_ex", "lbm_case_diverged_at", "lbm_set_launch_config", "lbm_autotune", "lbm_macros", "lbm_nusselt", "lbm_totals", "lbm_state_bytes",
+            "lbm_step_timed", "lbm_step_ex", "lbm_case_diverged_at", "lbm_set_launch_config",
+            "lbm_set_persistent_spin_limit", "lbm_autotune", "lbm_macros", "lbm_nusselt", "lbm_totals", "lbm_state_bytes",
             "lbm_save", "lbm_load", "lbm_time", "lbm_last_error", "lbm_destroy",
             "lbm_batch_create", "lbm_batch_size", "lbm_case_init", "lbm_case_init_static", "lbm_case_macros",
             "lbm_case_nusselt", "lbm_case_totals", "lbm_batch_flags", "lbm_batch_step", "lbm_batch_nusselt", "lbm_work_items",
@@ -257,15 +260,21 @@ class _Base:
             self._check(rc, "lbm_step_timed")
         return ms.value
 
-    def step_ex(self, n: int, graph: bool = False, allow_diverged: bool = False) -> float:
-        """Advance n steps (as one replayed HIP graph if ``graph``); return
-        their device time (ms)."""
+    def step_ex(self, n: int, graph: bool = False, allow_diverged: bool = False, persistent: bool = False) -> float:
+        """Advance n steps (as one replayed HIP graph if ``graph``; in one
+        launch of the persistent kernel if ``persistent``); return their
+        device time (ms)."""
         ms = C.c_double(0.0)
-        rc = self.lib.lbm_step_ex(self.h, int(n), STEP_GRAPH if graph else 0, C.byref(ms))
+        flags = (STEP_GRAPH if graph else 0) | (STEP_PERSISTENT if persistent else 0)
+        rc = self.lib.lbm_step_ex(self.h, int(n), flags, C.byref(ms))
         self.diverged = rc == EDIVERGED
         if not (rc == EDIVERGED and allow_diverged):
             self._check(rc, "lbm_step_ex")
         return ms.value
+
+    def set_persistent_spin_limit(self, polls: int):
+        self._check(self.lib.lbm_set_persistent_spin_limit(self.h, int(polls)), "lbm_set_persistent_spin_limit")
+        return self
 
     def diverged_at(self, k: int = 0) -> int:
         return int(self.lib.lbm_case_diverged_at(self.h, int(k)))
