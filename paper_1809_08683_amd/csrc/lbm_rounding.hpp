@@ -45,15 +45,17 @@ __host__ __device__ inline unsigned xorshift(unsigned w)
     return w;
 }
 __host__ __device__ inline unsigned rotl(unsigned w, int s) { return s == 0 ? w : (w << s) | (w >> (32 - s)); }
-// Random operand i of a node with mixed seed h: word i / 4 rotated left by
-// 8 (i % 4) bits, where word 0 is h and word k + 1 the xorshift32 step of
-// word k.  The four operands of a word have distinct top bytes (every byte
-// of every word is uniform); their lower bits overlap, which leaves each
-// rounding unbiased.
+// Random operand i of a node with mixed seed h: word i / 3 rotated left by
+// 10 (i % 3) bits, where word 0 is h and word k + 1 the xorshift32 step of
+// word k.  The rounding of a value depends on the top bits of its operand;
+// the three operands of a word have disjoint top 10-bit fields (bits 31-22,
+// 21-12, 11-2 of the word), so the roundings of a node's values are
+// independent to 2^-10 of an FP16 unit in the last place.
+constexpr int kOperandsPerWord = 3, kOperandShift = 10;
 __host__ __device__ inline unsigned operand(unsigned h, int i)
 {
-    for (int k = 0; k < (i >> 2); ++k) h = xorshift(h);
-    return rotl(h, 8 * (i & 3));
+    for (int k = 0; k < i / kOperandsPerWord; ++k) h = xorshift(h);
+    return rotl(h, kOperandShift * (i % kOperandsPerWord));
 }
 // random operand i of the node (x, y) (wrapped on a periodic axis) in step t
 __host__ __device__ inline unsigned operand_at(int x, int y, unsigned t, int i)

@@ -777,11 +777,11 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
                     Store<F>::bstore(ro, vf_out, q * frow_bytes, fb[q]);
                     continue;
                 }
-                if ((i >> 2) != wk) {
+                if (i / sr::kOperandsPerWord != wk) {
                     w = sr::xorshift(w);
-                    wk = i >> 2;
+                    wk = i / sr::kOperandsPerWord;
                 }
-                const unsigned rnd = sr::rotl(w, 8 * (i & 3));
+                const unsigned rnd = sr::rotl(w, sr::kOperandShift * (i % sr::kOperandsPerWord));
                 if (j < 9) Store<F>::bstore_sr(ro, vf_out, q * frow_bytes, fb[q], rnd);
                 else Store<G>::bstore_sr(ro, vg_out, g_base + q * grow_bytes, gb[q], rnd);
             }

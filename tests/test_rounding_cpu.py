@@ -16,8 +16,14 @@ NODES = ((0, 0), (1, 1), (517, 1023), (2047, 3))
 
 
 def _top_bytes(prec, x, y, rows):
+    """Top 8 bits of each operand (the rounding depends on the top bits)."""
     return np.array([[lbm.rounding_operand(prec, x, y, t, q) >> 24 for q in rows] for t in range(STEPS)],
                     dtype=float)
+
+
+def _top_fields(prec, x, y, rows, bits=10):
+    return np.array([[lbm.rounding_operand(prec, x, y, t, q) >> (32 - bits) for q in rows] for t in range(STEPS)],
+                    dtype=np.int64)
 
 
 @pytest.mark.parametrize("prec,rows", [("f16s", list(range(18))), ("f32g16", list(range(9, 18)))])
@@ -43,6 +49,24 @@ def test_rounding_operands_are_uniform_and_independent(prec, rows):
         prev = B
     a, b = _top_bytes(prec, 10, 20, rows), _top_bytes(prec, 11, 20, rows)
     assert max(abs(np.corrcoef(a[:, j], b[:, j])[0, 1]) for j in range(len(rows))) < r_limit
+
+
+@pytest.mark.parametrize("prec,rows", [("f16s", list(range(18))), ("f32g16", list(range(9, 18)))])
+def test_operands_of_a_node_share_no_top_bits(prec, rows):
+    """The top 10 bits of a node's operands come from disjoint bits of its
+    random words, so no two values of a node round alike by construction:
+    their fields agree only as often as independent uniform 10-bit numbers."""
+    F = _top_fields(prec, 3, 4, rows)
+    n = len(rows)
+    bits = (F[:, :, None] >> np.arange(10)[None, None, :]) & 1          # [step, value, bit]
+    limit = 5 * 0.5 / np.sqrt(STEPS)
+    for i in range(n):
+        for j in range(i + 1, n):
+            same = np.mean(F[:, i] == F[:, j])
+            assert same < 10.0 / 1024, (prec, rows[i], rows[j], same)
+            # no bit of one field follows a bit of the other (a shared bit agrees always)
+            agree = np.mean(bits[:, i, :, None] == bits[:, j, None, :], axis=0)
+            assert np.abs(agree - 0.5).max() < limit, (prec, rows[i], rows[j], np.abs(agree - 0.5).max())
 
 
 def test_rows_without_16_bit_storage_get_no_operand():
