@@ -37,14 +37,20 @@ def log(msg):
 
 
 def kernel_source_sha():
+    """Hash of the HIP sources with comments and whitespace removed, so that
+    a change of comments alone keeps a counter record valid."""
     import hashlib
     import glob
+    import re
     src = os.path.join(ROOT, "paper_1809_08683_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(src, "*.hip")) + glob.glob(os.path.join(src, "*.hpp"))):
         h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            code = fh.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

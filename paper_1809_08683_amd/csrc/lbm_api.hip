@@ -286,7 +286,7 @@ void build_case(lbm::CaseParams& P, int nx, int ny, const lbm_eos& e, double Pr,
 }
 
 // Work decomposition of one step.  The off-wall region of every case is cut
-// into strips of 60 columns and each strip into segments of nearly equal
+// into strips of 62 columns and each strip into segments of nearly equal
 // height; by default the number of segments is chosen so that all items of
 // a step are resident at once (one round of wavefronts).  Where the format
 // allows it, the strips next to an x-wall also collide its nodes (with

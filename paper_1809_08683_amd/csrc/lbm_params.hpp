@@ -59,7 +59,7 @@ struct CaseParams {
 };
 
 // One wavefront's share of a step.
-//   kind 0: interior strip, output columns [x0, x0 + 60) clipped to the off-wall
+//   kind 0: interior strip, output columns [x0, x0 + 62) clipped to the off-wall
 //           range, rows [y0, y0 + len), marched upwards (dir 0) or downwards (dir 1)
 //   kind 1: wall nodes [x0, x0 + len) of the case's wall-node enumeration
 struct WorkItem {
