@@ -62,17 +62,15 @@ using FmtF32G16 = Format<float, __half>;
 // whether the strips next to an x-wall collide its nodes (else wall items
 // take them; FP64 has no registers to spare for it), the time of a row of
 // such a strip relative to a plain row, and whether it loads the row two
-// ahead before the collision (where the registers allow it); the wavefronts
-// of a block (neighbouring strips of a segment share its CU); and whether a
-// wavefront lowers its priority as it advances (FP64 ran 0.6 % faster
-// without, the other formats 2-13 % slower).
-#ifndef LBM_PARK
-#define LBM_PARK 1
-#endif
+// ahead before the collision (where the registers allow it); whether the
+// moments of the row ahead wait in the wavefront's LDS slice during the
+// collision; the wavefronts of a block (neighbouring strips of a segment
+// share its CU); and whether a wavefront lowers its priority as it advances
+// (FP64 ran 0.6 % faster without, the other formats 2-13 % slower).
 template <typename Fm> struct Tuning;
 template <> struct Tuning<FmtF64> {
     static constexpr int block_waves = 8;
-    static constexpr bool park = LBM_PARK != 0;
+    static constexpr bool park = true;
     static constexpr int waves = 2;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
     static constexpr bool xw_strips = false, xw_prefetch = false;
@@ -81,7 +79,7 @@ template <> struct Tuning<FmtF64> {
 };
 template <> struct Tuning<FmtF32> {
     static constexpr int block_waves = 4;
-    static constexpr bool park = LBM_PARK != 0;
+    static constexpr bool park = true;
     static constexpr int waves = 3;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
     static constexpr bool xw_strips = true, xw_prefetch = true;
@@ -90,7 +88,7 @@ template <> struct Tuning<FmtF32> {
 };
 template <> struct Tuning<FmtF32G16> {
     static constexpr int block_waves = 4;
-    static constexpr bool park = LBM_PARK != 0;
+    static constexpr bool park = true;
     static constexpr int waves = 3;
     static constexpr bool lockstep = true, edge_select = true, alternate = true;
     static constexpr bool xw_strips = true, xw_prefetch = true;
@@ -99,7 +97,7 @@ template <> struct Tuning<FmtF32G16> {
 };
 template <> struct Tuning<FmtF16> {
     static constexpr int block_waves = 8;
-    static constexpr bool park = LBM_PARK != 0;
+    static constexpr bool park = true;
     static constexpr int waves = 4;
     static constexpr bool lockstep = false, edge_select = false, alternate = false;
     static constexpr bool xw_strips = true, xw_prefetch = false;
@@ -541,13 +539,10 @@ __device__ __forceinline__ void collide_interior(const CaseParams& P, const Coef
 // Wave priority from progress: a wavefront that has done less of its rows
 // is issued first, so the waves of a CU advance together and finish close to
 // each other instead of leaving a few young waves to run alone at the end.
-#ifndef LBM_FAIR
-#define LBM_FAIR 1
-#endif
 template <typename Fm>
 __device__ __forceinline__ void progress_priority(int done, int total)
 {
-    if constexpr (LBM_FAIR && Tuning<Fm>::fair) {
+    if constexpr (Tuning<Fm>::fair) {
         const int q = (4 * done) / total;      // 0..3 for done < total
         if (q == 0) __builtin_amdgcn_s_setprio(3);
         else if (q == 1) __builtin_amdgcn_s_setprio(2);
@@ -649,8 +644,11 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     const long long blk = blk_bytes;
     const int ylast_row = w.y0 + w.len - 1;
 
+    // values as loaded (FP16 rows stay FP16 until to_moments_raw)
+    using RF = typename Store<F>::Raw;
+    using RG = typename Store<G>::Raw;
     // pull lattice row yy: DF q comes from (x - e_qx, yy - e_qy)
-    auto pull = [&](int yy, C f[9], C g[9]) {
+    auto pull = [&](int yy, RF f[9], RG g[9]) {
         const rsrc_t r_s = make_rsrc(src + stored_row(yy - 1, ny, wall_y) * blk, blk_bytes);
         const rsrc_t r_c = make_rsrc(src + stored_row(yy, ny, wall_y) * blk, blk_bytes);
         const rsrc_t r_n = make_rsrc(src + stored_row(yy + 1, ny, wall_y) * blk, blk_bytes);
@@ -659,17 +657,17 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
             const rsrc_t r = EYq(q) == 1 ? r_s : (EYq(q) == 0 ? r_c : r_n);
             const int vf = EXq(q) == 1 ? vf0 : (EXq(q) == 0 ? vf1 : vf2);
             const int vg = EXq(q) == 1 ? vg0 : (EXq(q) == 0 ? vg1 : vg2);
-            f[q] = Store<F>::bload(r, vf, q * frow_bytes);
-            g[q] = Store<G>::bload(r, vg, g_base + q * grow_bytes);
+            f[q] = Store<F>::braw(r, vf, q * frow_bytes);
+            g[q] = Store<G>::braw(r, vg, g_base + q * grow_bytes);
         }
     };
     // A strip next to an x-wall has lanes on the wall column; their state
     // takes the wall velocity / temperature by selection (no divergence).
     const bool edge = Tuning<Fm>::edge_select && wall_x && (X - 1 <= 0 || X + STRIP_COLS >= nx - 1);
     // moments and state of a pulled row (wall rows: uniform branch to the wall formulas)
-    auto row_state = [&](int yy, const C f[9], const C g[9], C dm[9], C dn[9], NodeState<C>& st) {
-        to_moments<C>(f, dm);
-        to_moments<C>(g, dn);
+    auto row_state = [&](int yy, const RF f[9], const RG g[9], C dm[9], C dn[9], NodeState<C>& st) {
+        to_moments_raw(f, dm);
+        to_moments_raw(g, dn);
         if constexpr (has_gref<Fm>) {
             dn[1] += C(gref::m1) * sref;
             dn[2] += C(gref::m2) * sref;
@@ -698,7 +696,9 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     NodeState<C> s_c, s_n;          // current row, row ahead
     C rho_b, p_b;                   // row behind
     {
-        C f[9], g[9], dm[9], dn[9];
+        RF f[9];
+        RG g[9];
+        C dm[9], dn[9];
         NodeState<C> st;
         pull(yf - d, f, g);
         row_state(yf - d, f, g, dm, dn, st);
@@ -729,7 +729,8 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
         // ahead, which is in cache and whose state is not used) before the
         // collision
         const int ynext = i + 1 < w.len ? y + 2 * d : y + d;
-        C fr[9], gr[9];
+        RF fr[9];
+        RG gr[9];
         if constexpr (!XW || Tuning<Fm>::xw_prefetch) pull(ynext, fr, gr);
 
         // isotropic gradients d_a phi = 3 sum_q w_q e_qa phi(x + e_q), taken on
