@@ -101,36 +101,6 @@ __device__ __forceinline__ void to_moments(const C f[9], C m[9])
     m[8] = f[5] - f[6] + f[7] - f[8];
 }
 
-// The same transform of values as loaded (Store<>::braw).  FP16 values enter
-// every operation that reads them as an FMA with a multiplier of one held in
-// a scalar register the compiler cannot fold, x * 1 + y, which rounds as
-// x + y; the compiler then issues each as one v_fma_mix_f32 that converts its
-// FP16 operands itself, with no separate conversion instruction.
-__device__ __forceinline__ void to_moments_raw(const float f[9], float m[9]) { to_moments<float>(f, m); }
-__device__ __forceinline__ void to_moments_raw(const double f[9], double m[9]) { to_moments<double>(f, m); }
-__device__ __forceinline__ void to_moments_raw(const _Float16 h[9], float m[9])
-{
-    float one = 1.0f;
-    __asm__ volatile("" : "+s"(one));
-    auto v = [&](int q) { return float(h[q]); };
-    const float ax = __builtin_fmaf(v(1), one, v(3)), ay = __builtin_fmaf(v(2), one, v(4));
-    const float sx = __builtin_fmaf(v(1), one, -v(3)), sy = __builtin_fmaf(v(2), one, -v(4));
-    const float a = ax + ay;
-    const float p56 = __builtin_fmaf(v(5), one, v(6)), m56 = __builtin_fmaf(v(5), one, -v(6));
-    const float d = __builtin_fmaf(v(8), one, __builtin_fmaf(v(7), one, p56));
-    const float dx = __builtin_fmaf(v(8), one, __builtin_fmaf(v(7), -one, m56));
-    const float dy = __builtin_fmaf(v(8), -one, __builtin_fmaf(v(7), -one, p56));
-    m[0] = __builtin_fmaf(v(0), one, a) + d;
-    m[1] = __builtin_fmaf(2.0f, d, __builtin_fmaf(v(0), -4.0f, -a));
-    m[2] = __builtin_fmaf(v(0), 4.0f, -2.0f * a) + d;
-    m[3] = sx + dx;
-    m[4] = __builtin_fmaf(-2.0f, sx, dx);
-    m[5] = sy + dy;
-    m[6] = __builtin_fmaf(-2.0f, sy, dy);
-    m[7] = ax - ay;
-    m[8] = __builtin_fmaf(v(8), -one, __builtin_fmaf(v(7), one, m56));
-}
-
 template <typename C>
 __device__ __forceinline__ void from_moments(const C m[9], C f[9])
 {
@@ -647,7 +617,6 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes)
 
 template <> struct Store<double> {
     using C = double;
-    using Raw = double;   // a loaded value before its conversion to C
     static __device__ __forceinline__ void store_sr(double* p, double v, unsigned) { store(p, v); }
     static __device__ __forceinline__ void bstore_sr(rsrc_t r, int vo, int so, double v, unsigned) { bstore(r, vo, so, v); }
     static __device__ __forceinline__ double load(const double* p) { return *p; }
@@ -656,7 +625,6 @@ template <> struct Store<double> {
     {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
     }
-    static __device__ __forceinline__ double braw(rsrc_t r, int vo, int so) { return bload(r, vo, so); }
     static __device__ __forceinline__ void bstore(rsrc_t r, int vo, int so, double v)
     {
         using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
@@ -665,7 +633,6 @@ template <> struct Store<double> {
 };
 template <> struct Store<float> {
     using C = float;
-    using Raw = float;
     static __device__ __forceinline__ void store_sr(float* p, float v, unsigned) { store(p, v); }
     static __device__ __forceinline__ void bstore_sr(rsrc_t r, int vo, int so, float v, unsigned) { bstore(r, vo, so, v); }
     static __device__ __forceinline__ float load(const float* p) { return *p; }
@@ -674,7 +641,6 @@ template <> struct Store<float> {
     {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
     }
-    static __device__ __forceinline__ float braw(rsrc_t r, int vo, int so) { return bload(r, vo, so); }
     static __device__ __forceinline__ void bstore(rsrc_t r, int vo, int so, float v)
     {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, kStorePolicy);
@@ -682,7 +648,6 @@ template <> struct Store<float> {
 };
 template <> struct Store<__half> {
     using C = float;
-    using Raw = _Float16;   // converted where it is first used (to_moments_raw)
     // stochastic rounding with the random operand rnd (v_cvt_sr_f16_f32; lbm_rounding.hpp)
     static __device__ __forceinline__ unsigned short sr_bits(float v, unsigned rnd)
     {
@@ -715,10 +680,6 @@ template <> struct Store<__half> {
     {
         const unsigned short b = __builtin_bit_cast(unsigned short, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
         return __half2float(__ushort_as_half(b));
-    }
-    static __device__ __forceinline__ _Float16 braw(rsrc_t r, int vo, int so)
-    {
-        return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
     }
     static __device__ __forceinline__ void bstore(rsrc_t r, int vo, int so, float v)
     {

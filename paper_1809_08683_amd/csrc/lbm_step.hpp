@@ -644,11 +644,8 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     const long long blk = blk_bytes;
     const int ylast_row = w.y0 + w.len - 1;
 
-    // values as loaded (FP16 rows stay FP16 until to_moments_raw)
-    using RF = typename Store<F>::Raw;
-    using RG = typename Store<G>::Raw;
     // pull lattice row yy: DF q comes from (x - e_qx, yy - e_qy)
-    auto pull = [&](int yy, RF f[9], RG g[9]) {
+    auto pull = [&](int yy, C f[9], C g[9]) {
         const rsrc_t r_s = make_rsrc(src + stored_row(yy - 1, ny, wall_y) * blk, blk_bytes);
         const rsrc_t r_c = make_rsrc(src + stored_row(yy, ny, wall_y) * blk, blk_bytes);
         const rsrc_t r_n = make_rsrc(src + stored_row(yy + 1, ny, wall_y) * blk, blk_bytes);
@@ -657,17 +654,17 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
             const rsrc_t r = EYq(q) == 1 ? r_s : (EYq(q) == 0 ? r_c : r_n);
             const int vf = EXq(q) == 1 ? vf0 : (EXq(q) == 0 ? vf1 : vf2);
             const int vg = EXq(q) == 1 ? vg0 : (EXq(q) == 0 ? vg1 : vg2);
-            f[q] = Store<F>::braw(r, vf, q * frow_bytes);
-            g[q] = Store<G>::braw(r, vg, g_base + q * grow_bytes);
+            f[q] = Store<F>::bload(r, vf, q * frow_bytes);
+            g[q] = Store<G>::bload(r, vg, g_base + q * grow_bytes);
         }
     };
     // A strip next to an x-wall has lanes on the wall column; their state
     // takes the wall velocity / temperature by selection (no divergence).
     const bool edge = Tuning<Fm>::edge_select && wall_x && (X - 1 <= 0 || X + STRIP_COLS >= nx - 1);
     // moments and state of a pulled row (wall rows: uniform branch to the wall formulas)
-    auto row_state = [&](int yy, const RF f[9], const RG g[9], C dm[9], C dn[9], NodeState<C>& st) {
-        to_moments_raw(f, dm);
-        to_moments_raw(g, dn);
+    auto row_state = [&](int yy, const C f[9], const C g[9], C dm[9], C dn[9], NodeState<C>& st) {
+        to_moments<C>(f, dm);
+        to_moments<C>(g, dn);
         if constexpr (has_gref<Fm>) {
             dn[1] += C(gref::m1) * sref;
             dn[2] += C(gref::m2) * sref;
@@ -696,9 +693,7 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
     NodeState<C> s_c, s_n;          // current row, row ahead
     C rho_b, p_b;                   // row behind
     {
-        RF f[9];
-        RG g[9];
-        C dm[9], dn[9];
+        C f[9], g[9], dm[9], dn[9];
         NodeState<C> st;
         pull(yf - d, f, g);
         row_state(yf - d, f, g, dm, dn, st);
@@ -729,8 +724,7 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
         // ahead, which is in cache and whose state is not used) before the
         // collision
         const int ynext = i + 1 < w.len ? y + 2 * d : y + d;
-        RF fr[9];
-        RG gr[9];
+        C fr[9], gr[9];
         if constexpr (!XW || Tuning<Fm>::xw_prefetch) pull(ynext, fr, gr);
 
         // isotropic gradients d_a phi = 3 sum_q w_q e_qa phi(x + e_q), taken on
