@@ -102,9 +102,9 @@ typedef struct {
  *   FP16S  - FP16 storage of f and g, FP32 arithmetic, temperature in FP64;
  *   F32G16 - FP32 storage of the density DFs f, FP16 storage of the
  *            energy DFs g, FP32 arithmetic, temperature in FP64.
- * The 16-bit rows are rounded stochastically (unbiased; the random byte of a
- * value depends only on its node, row and step, so results are bitwise
- * reproducible), and with an ideal gas between two Dirichlet x-walls the g
+ * The 16-bit rows are rounded stochastically (unbiased; the random operand
+ * of a value depends only on where it is stored, its DF row and the step,
+ * so results are bitwise reproducible), and with an ideal gas between two Dirichlet x-walls the g
  * rows store offsets from the conduction state between them instead of the
  * global rest state.  On a cavity with eps = 0.6 the mean Nusselt number
  * then stays within 0.11 % (F32G16) and 0.45 % (FP16S; 0.9 % early in a

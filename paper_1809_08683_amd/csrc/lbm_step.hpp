@@ -801,7 +801,7 @@ __device__ __forceinline__ void interior_item(const CaseParams& P, const WorkIte
                 gka = C(gref::v_axis) * K.gsk;
                 gkd = C(gref::v_diag) * K.gsk;
             }
-            // random bytes of the ghost slots (column x -/+ 1, rows y, y + 1, y - 1)
+            // random operands of the ghost slots (column x -/+ 1, rows y, y + 1, y - 1)
             const int gcol = xl.left ? c - 1 : c + 1;
             const int yp = wrap_axis(y + 1, ny, wall_y), ym = wrap_axis(y - 1, ny, wall_y);
             if (has_left) {
