@@ -122,3 +122,40 @@ def density_profile(eos, T, mass):
         else:
             lo = p
     return rho_of(0.5 * (lo + hi))
+
+
+# ---------------------------------------------------------------------------
+# Constant-property channel flows on the benchmark grids (heated Couette
+# 3 x 64, van der Waals Poiseuille 3 x 128): incompressible start-up series
+# from rest and the steady closed forms.  eta = y / W, s = nu t / W^2.
+# ---------------------------------------------------------------------------
+def couette_startup(eta, s, terms=4000):
+    """u_x / U of a channel whose upper wall starts moving at U at t = 0
+    (lower wall at rest, fluid at rest): the steady eta minus the sine series
+    of eta, each mode decaying as exp(-(n pi)^2 s)."""
+    n = np.arange(1, terms + 1)[:, None]
+    modes = 2.0 * (-1.0) ** (n + 1) / (n * np.pi) * np.sin(n * np.pi * eta)
+    return eta - np.sum(modes * np.exp(-(n * np.pi) ** 2 * s), axis=0)
+
+
+def poiseuille_startup(eta, s, terms=4001):
+    """u_x / U0 of a force-driven channel started from rest, F = 8 mu U0 / W^2
+    (U0 the steady centre-line velocity): 4 eta (1 - eta) minus its sine
+    series (odd modes, coefficients 32 / (n pi)^3)."""
+    n = np.arange(1, terms + 1, 2)[:, None]
+    modes = 32.0 / (n * np.pi) ** 3 * np.sin(n * np.pi * eta)
+    return 4.0 * eta * (1.0 - eta) - np.sum(modes * np.exp(-(n * np.pi) ** 2 * s), axis=0)
+
+
+def heated_couette_steady(eta, U, T_bottom, T_top, Pr, cp=CP):
+    """Steady heated Couette flow with constant mu and lambda = C_p mu / Pr:
+    u = U eta and lambda T'' + mu (U / W)^2 = 0, so
+    T = T_b + (T_t - T_b) eta + (Pr U^2 / (2 C_p)) eta (1 - eta)."""
+    return U * eta, T_bottom + (T_top - T_bottom) * eta + Pr * U * U / (2.0 * cp) * eta * (1.0 - eta)
+
+
+def poiseuille_steady(eta, U0, T_wall, Pr, cp=CP):
+    """Steady force-driven channel with constant mu and lambda and both walls
+    at T_w: u = 4 U0 eta (1 - eta) and lambda T'' + mu u'^2 = 0, so
+    T = T_w + (Pr U0^2 / (3 C_p)) (1 - (1 - 2 eta)^4)."""
+    return 4.0 * U0 * eta * (1.0 - eta), T_wall + Pr * U0 * U0 / (3.0 * cp) * (1.0 - (1.0 - 2.0 * eta) ** 4)
