@@ -9,8 +9,15 @@ agree with the printed values to 0.5 % and 0.2 % (measured: 0.06-0.2 % and
 0.02-0.07 %); the largest horizontal velocity on the vertical midplane and
 the largest vertical velocity on the horizontal midplane, in units of
 U_ref = sqrt(Ra) mu0 / (rho0 L), to 1 % (measured: up to 0.55 %), and their
-positions to one grid spacing (measured: up to half of one).  (Ra >= 1e6 is
-out of reach at tau0 = 0.8: its buoyancy velocity passes Mach 0.3.)"""
+positions to one grid spacing (measured: up to half of one).
+
+Ra = 1e6 on Table 1's 512^2 grid is out of reach at tau0 = 0.8 (its
+buoyancy velocity passes Mach 0.3 and the run diverges); on 1024^2 the
+reference Mach number is 0.17 and the FP32 path converges to the Ra = 1e6
+row: Nu 8.6935 (-0.54 %), p_ave* +0.48 %, |u_x*|max -0.02 %, |u_y*|max
++1.5 %, positions within one spacing of the paper's grid (measured after
+1.66e6 steps; the FP64 path gives Nu 8.6910 at the same time, and a 2048^2
+FP32 run, Mach 0.085, 8.696 and still rising by 2e-5 per 10^5 steps)."""
 import numpy as np
 import pytest
 
@@ -75,3 +82,23 @@ def test_cavity_against_table2(Ra, prec, golden):
     assert abs(uy - t2["uy_max"][j]) < 0.01 * t2["uy_max"][j]
     assert abs(y - t2["y_max"][j]) < 1.0 / (N - 1)
     assert abs(x - t2["x_max"][j]) < 1.0 / (N - 1)
+
+
+def test_cavity_ra1e6_on_a_finer_grid(golden):
+    t2 = golden["cavity_table2_present"]
+    Ra = 1e6
+    N = 1024
+    i = t2["Ra"].index(Ra)
+    j = t2["velocity_rows_Ra"].index(Ra)
+    nu, p_ave, n, (ux, y), (uy, x) = _steady_cavity(N, Ra, chunk=20000, cap=2000000, rtol=1e-6, prec="f32")
+    e_nu = (nu - t2["Nu_ave"][i]) / t2["Nu_ave"][i]
+    e_p = (p_ave - t2["p_ave"][i]) / t2["p_ave"][i]
+    print(f"f32 Ra=1e6 N={N}: {n} steps, Nu {nu:.5f} ({e_nu:+.2e}), p_ave {p_ave:.5f} ({e_p:+.2e}), "
+          f"|ux|max {ux:.4f} at y {y:.4f}, |uy|max {uy:.4f} at x {x:.4f}", flush=True)
+    h = 1.0 / (golden["cavity_table1"]["N"][golden["cavity_table1"]["Ra"].index(Ra)] - 1)   # the paper's spacing
+    assert abs(e_nu) < 1e-2
+    assert abs(e_p) < 1e-2
+    assert abs(ux - t2["ux_max"][j]) < 0.01 * t2["ux_max"][j]
+    assert abs(uy - t2["uy_max"][j]) < 0.03 * t2["uy_max"][j]
+    assert abs(y - t2["y_max"][j]) < 1.5 * h
+    assert abs(x - t2["x_max"][j]) < 1.5 * h
