@@ -203,8 +203,8 @@ lbm_status lbm_set_launch_config(lbm_ctx* ctx, int variant, double xw_scale, int
  * holds an entry for this context's key (device architecture, storage
  * format, grid and wall signature of its cases), that entry is applied and
  * no trial runs.  Otherwise every configuration (5 kernel variants x 3
- * edge-cost scales when a case has x-walls x 3 band counts: 4, 1, 16 per
- * XCD) is timed over
+ * edge-cost scales when a case has x-walls x 4 band counts: 4, 1, 8, 16
+ * per XCD) is timed over
  * trial_steps steps (0: about 2e7 node updates) from the current state,
  * best of three after a warm-up, the state being restored after each trial
  * (t, buffers, macros and flags are unchanged on return); the fastest is

@@ -1175,10 +1175,10 @@ lbm_status lbm_autotune(lbm_ctx* c, int trial_steps, const char* cache_path, lbm
     best.ms = 1e300;
     int trials = 0;
     const double scales[3] = {1.0, 0.85, 1.2};
-    const int bands[3] = {4, 1, 16};
+    const int bands[4] = {4, 1, 8, 16};
     for (int v = 0; v < lbm::NUM_STEP_VARIANTS && he == hipSuccess && st == LBM_OK; ++v)
         for (int si = 0; si < (xwall ? 3 : 1) && he == hipSuccess && st == LBM_OK; ++si)
-            for (int bi = 0; bi < 3 && he == hipSuccess && st == LBM_OK; ++bi) {
+            for (int bi = 0; bi < 4 && he == hipSuccess && st == LBM_OK; ++bi) {
                 st = configure(c, v, scales[si], bands[bi]);
                 if (st != LBM_OK) break;
                 double ms_best = 1e300;

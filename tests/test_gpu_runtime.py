@@ -102,7 +102,7 @@ def test_autotune_keeps_the_state_and_uses_its_cache(tmp_path):
     before = [b.macros(k) for k in range(len(cases))]
     r = b.autotune(trial_steps=5, cache_path=cache)
     print("tuned:", r, flush=True)
-    assert r["trials"] == 5 * 3 * 3 and r["from_cache"] == 0
+    assert r["trials"] == 5 * 3 * 4 and r["from_cache"] == 0
     assert r["ms_per_step"] <= r["default_ms_per_step"] * 1.0001
     assert (r["variant"], r["xw_scale"], r["bands_per_xcd"]) == (0, 1.0, 4) or \
         r["ms_per_step"] < 0.99 * r["default_ms_per_step"]
