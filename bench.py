@@ -37,13 +37,16 @@ def log(msg):
 
 
 def kernel_source_sha():
-    """Hash of the HIP sources with comments and whitespace removed, so that
-    a change of comments alone keeps a counter record valid."""
+    """Hash of the HIP sources with comments and whitespace removed, and of
+    the compiler flags, so that a change of comments alone keeps a counter
+    record valid."""
     import hashlib
     import glob
     import re
+    from paper_1809_08683_amd import build as _build
     src = os.path.join(ROOT, "paper_1809_08683_amd", "csrc")
     h = hashlib.sha256()
+    h.update(" ".join(_build.HIPFLAGS).encode())
     for f in sorted(glob.glob(os.path.join(src, "*.hip")) + glob.glob(os.path.join(src, "*.hpp"))):
         h.update(os.path.basename(f).encode())
         with open(f, encoding="utf-8") as fh:

@@ -16,8 +16,13 @@ SOURCES = ["lbm_step_f32.hip", "lbm_step_f64.hip", "lbm_step_f16.hip", "lbm_step
            "lbm_kernels.hip", "lbm_api.hip"]
 HEADERS = ["lbm_device.hpp", "lbm_params.hpp", "lbm_launch.hpp", "lbm_step.hpp"]
 
-# Packed FP32 instructions are kept out of the generated code.
-HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+# Packed FP32 instructions are kept out of the generated code.  Multiply-adds
+# are fused only within one source expression (-ffp-contract=on): with the
+# default cross-statement fusion the compiler fused differently in different
+# inlined copies of the same node update, so a node at a work item's first
+# row could round differently from the same node inside another item, and
+# results depended on the launch configuration at the last-bit level.
+HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-munsafe-fp-atomics", "-Wall", "-Wno-unused-result"]
 

@@ -57,7 +57,7 @@ def test_every_launch_configuration_gives_the_same_state(prec):
     ref, cases = _batch(prec)
     ref.step(12)
     for variant in range(5):
-        for xw_scale, bands in ((1.0, 4), (0.85, 1), (1.2, 4)):
+        for xw_scale, bands in ((1.0, 4), (0.85, 1), (1.2, 16)):
             print(f"{prec}: variant {variant} xw_scale {xw_scale} bands {bands}", flush=True)
             b, _ = _batch(prec)
             b.set_launch_config(variant, xw_scale, bands)
