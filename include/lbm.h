@@ -104,11 +104,12 @@ typedef struct {
  *            energy DFs g, FP32 arithmetic, temperature in FP64.
  * The 16-bit rows are rounded stochastically (unbiased; the random operand
  * of a value depends only on where it is stored, its DF row and the step,
- * so results are bitwise reproducible), and with an ideal gas between two Dirichlet x-walls the g
- * rows store offsets from the conduction state between them instead of the
- * global rest state.  On a cavity with eps = 0.6 the mean Nusselt number
- * then stays within 0.11 % (F32G16) and 0.45 % (FP16S; 0.9 % early in a
- * 1024^2 transient) of FP64 up to 2048^2; FP32 within 5e-4. */
+ * so results are bitwise reproducible), and with an ideal gas between two
+ * Dirichlet x-walls the g rows store offsets from the conduction state
+ * between them instead of the global rest state.  On a cavity with
+ * eps = 0.6 the mean Nusselt number then stays within 0.2 % (F32G16) and
+ * 0.5 % (FP16S; 0.6 % early in a 1024^2 transient) of FP64 up to 2048^2;
+ * FP32 within 6e-4. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2, LBM_F32G16 = 3 } lbm_precision;
 
 typedef struct {

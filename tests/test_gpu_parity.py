@@ -392,7 +392,7 @@ def test_nusselt_cavity_256_against_table2_and_fp64(golden):
 
 def test_fp16s_nusselt_within_half_percent_of_fp64():
     """The same cavity in the FP16-offset format held to the 0.5 % bar
-    (measured: 4e-4; with rounding to nearest instead of stochastic
+    (measured: 1.6e-4; with rounding to nearest instead of stochastic
     rounding it was 12 %)."""
     nu16, nu64 = _nu256("f16s"), _nu256("f64")
     rel = (nu16 - nu64) / nu64
@@ -426,15 +426,16 @@ def _rel_fine(prec):
 
 def test_fp32_nusselt_tracks_fp64_on_a_fine_grid():
     """Over 75 000 steps of the 1024^2 transient the FP32 path's Nu stays
-    within 1e-3 of the FP64 path's at every 25 000 steps (measured: 4e-4)."""
+    within 1e-3 of the FP64 path's at every 25 000 steps (measured: 4.1e-4)."""
     assert max(abs(r) for r in _rel_fine("f32")) < 1e-3
 
 
 def test_16bit_nusselt_tracks_fp64_on_a_fine_grid():
     """The same transient in the 16-bit formats.  FP32 f + FP16 g stays
-    within the 0.5 % bar at every check (measured: 9e-4); FP16S is within
-    1 % at 25 000 steps, where Nu still changes fastest (measured: 0.9 %),
-    and within 0.5 % after (measured: 1e-3).  With rounding to nearest and
+    within the 0.5 % bar at every check (measured: 1.0e-3); FP16S is within
+    1 % at 25 000 steps, where Nu still changes fastest (measured: 0.61 %),
+    and within 0.5 % after (measured: 0.48 % and 0.06 %; a change of the
+    last bit anywhere moves these by about 0.1 %).  With rounding to nearest and
     no reference state for g, these errors were 2-14 % (FP32 f + FP16 g)
     and several times Nu (FP16S)."""
     rel = _rel_fine("f32g16")
