@@ -1110,7 +1110,12 @@ __attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
 
 
 // Arrive at the end of a step and wait for the case's other wavefronts;
-// false if the wait was abandoned.
+// false if the wait was abandoned.  Fence-to-fence synchronisation: the
+// release fence orders the step's stores before the relaxed arrival, and
+// the acquire fence after the wait orders the next step's loads after it.
+// The polls themselves are relaxed: an acquire load at device scope makes
+// the wavefront invalidate its XCD's L2 after every poll, which costs every
+// other wavefront on that XCD its cached lines.
 __device__ __forceinline__ bool case_barrier(const PersistentSync& S, int case_id, unsigned target)
 {
     int ok = 1;
@@ -1118,9 +1123,9 @@ __device__ __forceinline__ bool case_barrier(const PersistentSync& S, int case_i
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if ((threadIdx.x & (WAVE - 1)) == 0) {
         unsigned* cnt = S.counter + case_id;
-        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned polls = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(S.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                 ok = 0;
                 break;
