@@ -94,7 +94,7 @@ struct lbm_ctx {
     // resident at once
     unsigned* d_pcount = nullptr;
     int* d_pabort = nullptr;
-    int* d_case_waves = nullptr;
+    int* d_case_arrivals = nullptr;
     bool persistent_ok = false;
     std::string persistent_why;
     unsigned spin_limit = 1u << 24;      // polls of a persistent step barrier before it gives up
@@ -520,13 +520,22 @@ lbm_status configure(lbm_ctx* c, int variant, double xw_scale, int bands_per_xcd
     }
     HIP_TRY(c, hipMemcpyAsync(c->d_work, c->work.data(), sizeof(lbm::WorkItem) * c->work.size(),
                               hipMemcpyHostToDevice, c->stream));
-    // persistent stepping: wavefronts per case, and whether all blocks of
-    // the persistent kernel are resident at once
+    // persistent stepping: arrivals per step of each case (one per block
+    // that holds an item of it), and whether all blocks of the persistent
+    // kernel are resident at once
     const int nc = int(c->P.size());
-    std::vector<int> waves(size_t(nc), 0);
-    for (const auto& w : c->work)
-        if (w.kind != 2) ++waves[size_t(w.case_id)];
-    if (!c->d_case_waves) {
+    std::vector<int> arrivals(size_t(nc), 0);
+    const size_t bw = size_t(std::max(sh.block_waves, 1));
+    for (size_t b0 = 0; b0 < c->work.size(); b0 += bw) {
+        std::vector<int> seen;
+        for (size_t k = b0; k < std::min(b0 + bw, c->work.size()); ++k) {
+            const lbm::WorkItem& w = c->work[k];
+            if (w.kind == 2 || std::find(seen.begin(), seen.end(), w.case_id) != seen.end()) continue;
+            seen.push_back(w.case_id);
+            ++arrivals[size_t(w.case_id)];
+        }
+    }
+    if (!c->d_case_arrivals) {
         void* p1 = nullptr;
         void* p2 = nullptr;
         void* p3 = nullptr;
@@ -536,11 +545,11 @@ lbm_status configure(lbm_ctx* c, int variant, double xw_scale, int bands_per_xcd
             if (p2) (void)hipFree(p2);
             return fail(c, LBM_ENOMEM, "hipMalloc of the persistent-step words failed");
         }
-        c->d_case_waves = static_cast<int*>(p1);
+        c->d_case_arrivals = static_cast<int*>(p1);
         c->d_pcount = static_cast<unsigned*>(p2);
         c->d_pabort = static_cast<int*>(p3);
     }
-    HIP_TRY(c, hipMemcpyAsync(c->d_case_waves, waves.data(), sizeof(int) * size_t(nc), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_case_arrivals, arrivals.data(), sizeof(int) * size_t(nc), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     int pbpc = 0;
     const int pe = lbm::persistent_blocks(c->prec, variant, &pbpc);
@@ -683,7 +692,7 @@ int enqueue_persistent(lbm_ctx* c, long long n, int parity)
 {
     int rc = lbm::launch_persistent_reset(c->d_pcount, int(c->P.size()), c->d_pabort, c->stream);
     if (rc != 0) return rc;
-    const lbm::PersistentSync sync{c->d_pcount, c->d_pabort, c->d_case_waves, c->spin_limit};
+    const lbm::PersistentSync sync{c->d_pcount, c->d_pabort, c->d_case_arrivals, c->spin_limit};
     return lbm::launch_persistent(c->prec, c->variant, c->d_P, c->d_work, int(c->work.size()), parity, int(n), sync,
                                   c->stream);
 }
@@ -1459,7 +1468,7 @@ void lbm_destroy(lbm_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
     if (c->d_work) (void)hipFree(c->d_work);
-    if (c->d_case_waves) (void)hipFree(c->d_case_waves);
+    if (c->d_case_arrivals) (void)hipFree(c->d_case_arrivals);
     if (c->d_pcount) (void)hipFree(c->d_pcount);
     if (c->d_pabort) (void)hipFree(c->d_pabort);
     for (void* p : c->allocs) (void)hipFree(p);

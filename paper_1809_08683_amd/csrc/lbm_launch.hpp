@@ -23,7 +23,7 @@ struct StepShape {
 struct PersistentSync {
     unsigned* counter;      // per case, step arrivals (reset to 0 before the launch)
     int* abort;             // nonzero: a wait timed out, all wavefronts leave
-    const int* case_waves;  // per case, the wavefronts with an item of the case
+    const int* case_arrivals;  // per case, arrivals per step: the blocks with an item of the case
     unsigned spin_limit;    // polls before a wait gives up
 };
 

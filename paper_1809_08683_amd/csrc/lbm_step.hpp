@@ -1093,52 +1093,58 @@ __attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void step_kernel(
 
 // ---------------------------------------------------------------------------
 // persistent kernel: n steps in one launch.  Every wavefront keeps its work
-// item for all n steps; between two steps it waits until all wavefronts of
-// its case have finished the step (a per-case counter, incremented with
-// release and polled with acquire semantics at device scope), so the cases
-// of a batch advance independently and no launch boundary separates the
-// steps.  The host launches it only if every block is resident at once
-// (checked against the kernel's occupancy), so every awaited wavefront runs;
-// every wait is bounded all the same: after `spin_limit` polls the
-// wavefront raises the abort word and all wavefronts leave, so the kernel
-// always ends.  In lockstep formats the waves of a block meet at a barrier
-// per row; a wavefront whose item is shorter than the longest one of its
-// block executes the missing barriers at the end of each step, so the
-// waves of a block meet the same number of barriers per step and none waits
-// on a wave that is already waiting at its case barrier.
+// item for all n steps.  Between two steps the waves of a block meet at a
+// barrier, and then one of them (the block's first wavefront with an item)
+// arrives, once for each case among the block's items, at that case's
+// counter and waits until every block holding the case has arrived (release
+// and acquire at device scope), so the cases of a batch advance
+// independently and no launch boundary separates the steps.  The host
+// launches it only if every block is resident at once (checked against the
+// kernel's occupancy), so every awaited block runs; every wait is bounded
+// all the same: after `spin_limit` polls the waiting wavefront raises the
+// abort word and every block leaves, so the kernel always ends.  In
+// lockstep formats the waves of a block also meet at a barrier per row; a
+// wavefront whose item is shorter than the longest one of its block
+// executes the missing barriers at the end of each step, so the waves of a
+// block meet the same number of barriers per step.
 // ---------------------------------------------------------------------------
 
 
-// Arrive at the end of a step and wait for the case's other wavefronts;
-// false if the wait was abandoned.  Fence-to-fence synchronisation: the
-// release fence orders the step's stores before the relaxed arrival, and
-// the acquire fence after the wait orders the next step's loads after it.
-// The polls themselves are relaxed: an acquire load at device scope makes
-// the wavefront invalidate its XCD's L2 after every poll, which costs every
-// other wavefront on that XCD its cached lines.
-__device__ __forceinline__ bool case_barrier(const PersistentSync& S, int case_id, unsigned target)
+// The leader's part of a block's step barrier: arrive at the counters of the
+// block's cases (ids[0 .. n)) and wait until each has reached `step` times
+// its arrivals per step; false if the wait was abandoned.  Fence-to-fence
+// synchronisation: the release fence orders the block's stores of the step
+// (gathered by the block barrier before it) before the relaxed arrivals,
+// and the acquire fence after the wait orders the next step's loads after
+// it.  The polls themselves are relaxed: an acquire load at device scope
+// makes the wavefront invalidate its XCD's L2 after every poll, which costs
+// every other wavefront on that XCD its cached lines.
+__device__ __forceinline__ bool case_barrier(const PersistentSync& S, const int* ids, int n, unsigned step)
 {
     int ok = 1;
-    // every lane's stores of the step, released before the arrival
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if ((threadIdx.x & (WAVE - 1)) == 0) {
-        unsigned* cnt = S.counter + case_id;
-        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < n; ++k)
+            __hip_atomic_fetch_add(S.counter + ids[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned polls = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(S.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                ok = 0;
-                break;
+        for (int k = 0; k < n && ok; ++k) {
+            const unsigned* cnt = S.counter + ids[k];
+            const unsigned target = unsigned(S.case_arrivals[ids[k]]) * step;
+            while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (__hip_atomic_load(S.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    ok = 0;
+                    break;
+                }
+                if (++polls > S.spin_limit) {
+                    __hip_atomic_store(S.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
             }
-            if (++polls > S.spin_limit) {
-                __hip_atomic_store(S.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
         }
     }
-    // lane 0's outcome for the whole wavefront, and the acquire for its loads
+    // lane 0's outcome for the whole wavefront, and the acquire for the block
     ok = __builtin_amdgcn_readfirstlane(ok);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return ok != 0;
@@ -1155,19 +1161,24 @@ __attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void persistent_kerne
     if (wid >= nwork) return;
     const WorkItem w = load_item(work, wid);
     if (w.kind == 2) return;
-    // row barriers per step of the block's longest interior item
-    int rows_max = 0;
-    if constexpr (Tuning<Fm>::lockstep) {
-        const int first = wid - (threadIdx.x >> 6);
-        for (int k = 0; k < PB && first + k < nwork; ++k) {
-            const WorkItem o = load_item(work, first + k);
-            if (o.kind == 0) rows_max = max(rows_max, o.len);
-        }
+    // the block's items: the longest interior one (row barriers per step),
+    // its first wavefront with an item (the leader) and its cases
+    const int first = wid - (threadIdx.x >> 6);
+    int rows_max = 0, leader = -1, ncase = 0;
+    int ids[PB];
+    for (int k = 0; k < PB && first + k < nwork; ++k) {
+        const WorkItem o = load_item(work, first + k);
+        if (o.kind == 2) continue;
+        if (o.kind == 0) rows_max = max(rows_max, o.len);
+        if (leader < 0) leader = first + k;
+        bool seen = false;
+        for (int j = 0; j < ncase; ++j) seen = seen || ids[j] == o.case_id;
+        if (!seen) ids[ncase++] = o.case_id;
     }
+    __shared__ int abandoned;
     const CaseParams& P = case_of(cases, w.case_id);
     unsigned tk0 = 0u;
     if constexpr (sr::used<Fm>) tk0 = __builtin_amdgcn_readfirstlane(*as_global<unsigned>(P.tick + parity));
-    const unsigned waves = unsigned(S.case_waves[w.case_id]);
     using C = typename Fm::C;
     __shared__ C park_lds[Tuning<Fm>::park ? PB * 18 * WAVE : 1];
     C* park = park_lds + (Tuning<Fm>::park ? (threadIdx.x >> 6) * 18 * WAVE : 0);
@@ -1184,7 +1195,15 @@ __attribute__((amdgpu_waves_per_eu(Tuning<Fm>::waves, 8))) void persistent_kerne
             const int own = w.kind == 0 ? w.len : 0;
             for (int i = own; i < rows_max; ++i) __syncthreads();
         }
-        if (s + 1 < nsteps && !case_barrier(S, w.case_id, waves * unsigned(s + 1))) return;
+        if (s + 1 < nsteps) {
+            __syncthreads();   // the block's stores of the step, gathered for the leader's release
+            if (wid == leader) {
+                const bool ok = case_barrier(S, ids, ncase, unsigned(s + 1));
+                if ((threadIdx.x & (WAVE - 1)) == 0) abandoned = ok ? 0 : 1;
+            }
+            __syncthreads();   // the leader's acquire, passed on to the block
+            if (abandoned) return;
+        }
     }
 }
 
